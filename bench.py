@@ -1,0 +1,205 @@
+"""FDAS hot-path benchmark on one MI355X.
+
+One step = the whole hot path on one SKA-sized spectrum already resident in
+HBM: fdas_convolve (85-template FT convolution + power -> FOP), then
+fdas_harmonic_sum (8 harmonic planes, thresholds, candidate compaction), then
+fdas_candidates (readback + canonical order).  Template generation happens
+once at plan creation and is not timed.
+
+Prints one JSON line.  Per-kernel durations come from HIP events recorded on
+the stream the library launches on; the roofline object describes the kernel
+with the longest average duration.  The CPU baseline times the FP64 oracle
+on a bounded sample (the first 2^20 bins of the same spectrum) and scales it
+to spectra/s of the full 2^22 workload.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FDAS spectra/s (2^22 pts, 85 templates, 8 harmonics) + % HBM/MFMA roofline"
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TF = 157.3  # MI355X FP32 vector, published
+
+
+def kernel_source_digest(name):
+    path = os.path.join(ROOT, "paper_1806_01556_amd", "csrc", name)
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(kernel_file, launches_bytes_key):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None.
+
+    The summary carries a line `traffic: {json}` with the kernel source digest
+    at the time the counters were taken; a different digest means stale
+    counters, reported as null.
+    """
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            m = re.match(r"^traffic:\s*(\{.*\})\s*$", line.strip())
+            if not m:
+                continue
+            rec = json.loads(m.group(1))
+            if rec.get("kernel_file") != kernel_file:
+                continue
+            if rec.get("source_digest") != kernel_source_digest(kernel_file):
+                return None
+            return rec.get(launches_bytes_key)
+    return None
+
+
+def cpu_baseline(spec, n_full):
+    """FP64 oracle on the first 2^20 bins of the spectrum, scaled to the full length."""
+    from oracle import fop as ofop
+    from oracle import harmonic as oh
+
+    n_s = min(1 << 20, spec.shape[0])
+    workers = max(1, min(16, os.cpu_count() or 1))
+    x = spec[:n_s].astype(np.complex128)
+    t0 = time.perf_counter()
+    plane = ofop.fop(x, workers=workers)
+    cands = oh.candidates(plane, 8)
+    dt = time.perf_counter() - t0
+    return {
+        "value": (n_s / n_full) / dt,
+        "unit": "spectra/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": f"first {n_s} bins of the same spectrum as one {n_s}-point spectrum "
+                  f"(FP64 FFT correlation, {workers} scipy.fft workers, + harmonic sum), "
+                  f"{dt:.1f} s, scaled by {n_s}/{n_full}; {cands.size} candidates",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(spectra are independent, so several GPUs would each run this same workload)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1806_01556_amd import fdas, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    fdas.lib()  # raises if libfdas.so is missing
+
+    n = 1 << 22
+    spec, pulsars = synth.ska(n=n, seed=2)
+    x = torch.from_numpy(spec).to(dev)
+    plan = fdas.plan_create(n_max=n)
+    fop = fdas.alloc_fop(plan, n, dev)
+    cands, counts = fdas.alloc_cands(plan, dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev:
+            ev[0].record(stream)
+        fdas.convolve(plan, x, fop, n=n, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        fdas.harmonic_sum(plan, fop, n, cands, counts, stream=stream)
+        if ev:
+            ev[2].record(stream)
+        c, hc = fdas.candidates(plan, cands, counts, stream=stream, allow_overflow=True)
+        return c, hc
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ncand = 0
+    for k in range(args.steps):
+        c, hc = step(evs[k])
+        ncand = int(c.size)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    conv_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    hs_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ms_per_step = 1e3 * wall / args.steps
+    readback_ms = max(0.0, ms_per_step - conv_ms - hs_ms)
+
+    V = 4096 - 393                                    # valid outputs per 4096-point chunk
+    conv_flop = 85 * 5 * 4096 * 12 / V * n          # algorithmic FFT flops of one launch
+    hs_bytes = 4 * 85 * n                            # FOP read once
+    conv_bytes = 8 * n + 4 * 85 * n                  # spectrum read + FOP write
+    kernels = {
+        "k_ols_conv": {"ms": conv_ms, "bound": "alu", "achieved": conv_flop / (conv_ms * 1e-3) / 1e12,
+                       "peak": FP32_VECTOR_PEAK_TF, "unit": "TFLOP/s", "file": "k_ols_conv.hip",
+                       "hbm_gbs": conv_bytes / (conv_ms * 1e-3) / 1e9},
+        "k_harmsum": {"ms": hs_ms, "bound": "hbm", "achieved": hs_bytes / (hs_ms * 1e-3) / 1e9,
+                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "file": "k_harmsum.hip"},
+    }
+    dom_name = max(kernels, key=lambda k: kernels[k]["ms"])
+    dom = kernels[dom_name]
+    roof = {
+        "kernel": dom_name,
+        "bound": dom["bound"],
+        "achieved": round(dom["achieved"], 3),
+        "peak": dom["peak"],
+        "unit": dom["unit"],
+        "frac": round(dom["achieved"] / dom["peak"], 4),
+        "traffic": read_traffic(dom["file"], "bytes_per_launch"),
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": round(args.steps / wall, 3),
+        "unit": "spectra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "ska_single_spectrum_2^22", "n": n, "templates": 85, "z_max": 42,
+                   "harmonics": 8, "p_fa": 1e-6, "pulsars": len(pulsars), "seed": 2,
+                   "method": "ols_fft_c4096"},
+        "roofline": roof,
+        "stages_ms": {"convolve": round(conv_ms, 4), "harmonic_sum": round(hs_ms, 4),
+                      "candidates_readback": round(readback_ms, 4)},
+        "kernels": {k: {"avg_ms": round(v["ms"], 4), "achieved": round(v["achieved"], 3), "unit": v["unit"],
+                        "frac": round(v["achieved"] / v["peak"], 4)} for k, v in kernels.items()},
+        "conv_hbm_gbs": round(kernels["k_ols_conv"]["hbm_gbs"], 1),
+        "device_spectra_per_s": round(1e3 / (conv_ms + hs_ms), 2),
+        "candidates": ncand,
+        "candidates_per_plane": [int(v) for v in hc],
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec, n)
+    plan.destroy()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

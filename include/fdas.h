@@ -1,0 +1,175 @@
+/*
+ * fdas.h -- C ABI of libfdas, the MI355X (gfx950) FDAS hot path.
+ *
+ * FDAS (Fourier-domain acceleration search) as described by Wang, Thiagaraj &
+ * Sinnen, "Combining Multiple Optimized FPGA-based Pulsar Search Modules Using
+ * OpenCL", has two steps, and this library exposes one call for each:
+ *
+ *   fdas_convolve      Section 2.1 (eq. (1) / eq. (2)): the complex spectrum is
+ *                      correlated with N_temp = 2*z_max+1 acceleration templates
+ *                      (85 in Table 1) and the power of every output is written
+ *                      to the filter-output plane (FOP), rows = templates,
+ *                      columns = Fourier bins.
+ *   fdas_harmonic_sum  Section 2.2, Algorithm 1: the FOP is stretched by
+ *                      k = 1..N_hp (8 in Table 1), the harmonic planes
+ *                      HP_k = HP_{k-1} + SP_k are formed without being stored,
+ *                      every cell is compared with the threshold TA(k, i), and
+ *                      cells above it are appended to per-plane candidate lists.
+ *   fdas_candidates    copies the lists back and returns them in the loop order
+ *                      of Algorithm 1, (k, i, j), optionally keeping N_cand per
+ *                      plane (200 in Table 1).
+ *
+ * Conventions (all calls):
+ *   - Every pointer named d_* is device memory on the plan's device, allocated
+ *     and owned by the caller.  h_* pointers are host memory owned by the caller.
+ *     The plan owns its templates, twiddle tables and workspace.
+ *   - Arguments are validated before anything is launched; on error nothing
+ *     has been written and the call has no side effect.  fdas_last_error()
+ *     returns a thread-local message describing the last failure.
+ *   - fdas_convolve and fdas_harmonic_sum are asynchronous on `stream`
+ *     (a hipStream_t; NULL = the default stream).  fdas_plan_create,
+ *     fdas_plan_destroy and fdas_candidates synchronise.
+ *   - A plan may be used from one stream at a time (not re-entrant).
+ *   - Readings of passages the paper leaves open (template formula, z step,
+ *     alignment, stretch, thresholds) are fixed by this library as stated at
+ *     each call.
+ */
+#ifndef FDAS_H
+#define FDAS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FDAS_ABI_VERSION 1
+
+typedef enum {
+  FDAS_OK = 0,
+  FDAS_ERR_INVALID_ARG = 1,   /* bad pointer, size, layout or descriptor field */
+  FDAS_ERR_NO_DEVICE = 2,     /* no usable GPU, or desc.device out of range */
+  FDAS_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed */
+  FDAS_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+  FDAS_ERR_CAPACITY = 5,      /* a candidate list overflowed (counts stay exact) */
+  FDAS_ERR_UNSUPPORTED = 6    /* valid request that this build does not provide */
+} fdas_status;
+
+/* FT-convolution method (Section 2.1). */
+enum {
+  FDAS_CONV_AUTO = 0,     /* the faster of the two on this GPU (overlap-save) */
+  FDAS_CONV_OLS_FFT = 1,  /* overlap-save FFT correlation (Section 2.1.2, eq. (2)) */
+  FDAS_CONV_DIRECT = 2    /* direct complex FIR sum on the matrix cores (eq. (1)) */
+};
+
+/* Arithmetic of the direct method (the overlap-save method is always FP32). */
+enum {
+  FDAS_PREC_FP32 = 0
+};
+
+/* Harmonic index map used by fdas_harmonic_sum. */
+enum {
+  FDAS_HSUM_STRETCH = 0   /* SP_k(i, j) = FOP(trunc(i/k), floor(j/k)) */
+};
+
+typedef struct {
+  int32_t struct_size;   /* sizeof(fdas_plan_desc); guards ABI drift */
+  int32_t z_max;         /* templates z = -z_max..z_max (row = z + z_max); 0..64, default 42 */
+  int64_t n_max;         /* largest spectrum length the plan accepts; >= 1 */
+  int32_t n_harm;        /* harmonic planes N_hp, 1..8, default 8 */
+  int32_t cand_capacity; /* candidates stored per plane on the device, >= 1 */
+  double  p_fa;          /* per-cell false-alarm probability of the default TA, (0, 1) */
+  int32_t top_k;         /* fdas_candidates keeps this many per plane (0 = all; 200 = Table 1) */
+  int32_t method;        /* FDAS_CONV_* */
+  int32_t precision;     /* FDAS_PREC_* */
+  int32_t hsum_index;    /* FDAS_HSUM_* */
+  int32_t ols_chunk;     /* overlap-save FFT length; 0 = default (4096); only 4096 is built */
+  int32_t device;        /* HIP device ordinal */
+} fdas_plan_desc;
+
+/* One candidate: harmonic plane k (1-based), template z (= row - z_max),
+ * Fourier bin r, and the FP32 harmonic sum HP_k(z, r).  16 bytes. */
+typedef struct {
+  int32_t harm;
+  int32_t z;
+  int32_t r;
+  float power;
+} fdas_cand;
+
+typedef struct fdas_plan fdas_plan;
+
+/* Fill *desc with the defaults: z_max 42, n_harm 8, p_fa 1e-6, n_max 2^22,
+ * cand_capacity 65536, top_k 0, AUTO method, FP32, stretch index, device 0. */
+void fdas_plan_desc_default(fdas_plan_desc* desc);
+
+/* Create a plan (Table 1 sizes by default).  Builds the 2*z_max+1 templates in
+ * FP64 from the Fourier-domain acceleration response (the paper names the
+ * Ransom et al. correlation technique without printing coefficients):
+ *   A(q, z) = integral_0^1 exp(i*pi*(z u^2 + (2q - z) u)) du,
+ *   h_z[d]  = conj(A(-d, z)) / sqrt(sum_d |A(-d, z)|^2),
+ *   d in [-L/2, L/2 - 1],  L(z) = 2*(8 + ceil(4.5*|z|))  (<= 400 taps, Section 1),
+ * their overlap-save spectra, the default thresholds TA(k, i) = Q^{-1}(k, p_fa)
+ * (inverse regularised upper incomplete gamma), and uploads them.
+ * Returns FDAS_ERR_NO_DEVICE when no GPU is present; *out is NULL on error. */
+fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out);
+
+/* Release a plan and its device memory.  NULL is a no-op.  Synchronises. */
+fdas_status fdas_plan_destroy(fdas_plan* plan);
+
+/* FT convolution + power (Section 2.1, eq. (1)/(2); power as in Section 2.2):
+ *   d_fop[(z + z_max) * ld + j] = | sum_d X[j + d] h_z[d] |^2,  j in [0, n),
+ * X[k] = 0 outside [0, n) (both ends zero-extended), column j = bin j.
+ * d_spectrum: complex64[n] (interleaved re, im), 8-byte aligned.
+ * d_fop: float[(2*z_max+1) * ld], 16-byte aligned, ld >= n and ld % 4 == 0.
+ * 1 <= n <= n_max.  Asynchronous on stream.  Columns >= n are not written. */
+fdas_status fdas_convolve(fdas_plan* plan, const void* d_spectrum, int64_t n,
+                          float* d_fop, int64_t ld, void* stream);
+
+/* Harmonic summing with threshold detection (Algorithm 1, Section 2.2):
+ *   HP_1 = FOP, HP_k(i, j) = HP_{k-1}(i, j) + FOP(trunc(i/k), floor(j/k)),
+ * summed in FP32 in k order; a cell with HP_k(i, j) > TA(k, i) is appended to
+ * list k-1.  d_ta: float[n_harm][2*z_max+1] or NULL for the plan's default.
+ * d_cands: fdas_cand[n_harm][cand_capacity]; d_counts: int32[n_harm].
+ * d_counts is reset by this call and ends holding the true number of cells
+ * above threshold per plane, also when that exceeds cand_capacity (then only
+ * cand_capacity records, in no particular order, are stored).  The order of
+ * records inside a list is unspecified; fdas_candidates sorts them.
+ * Same FOP layout rules as fdas_convolve.  Asynchronous on stream. */
+fdas_status fdas_harmonic_sum(fdas_plan* plan, const float* d_fop, int64_t n, int64_t ld,
+                              const float* d_ta, fdas_cand* d_cands, int32_t* d_counts,
+                              void* stream);
+
+/* Copy the candidate lists back (after the work queued on stream), order them
+ * by (harm, z, r) and write at most h_capacity records to h_out.  With
+ * top_k > 0 each plane keeps its top_k highest powers (ties: lower z, then
+ * lower r, first) before ordering.  *h_n receives the number written.
+ * h_counts (optional, int32[n_harm]) receives the device counts.
+ * Returns FDAS_ERR_CAPACITY if a device list overflowed or h_capacity was too
+ * small; the records returned are then still ordered but incomplete. */
+fdas_status fdas_candidates(fdas_plan* plan, const fdas_cand* d_cands, const int32_t* d_counts,
+                            fdas_cand* h_out, int64_t h_capacity, int64_t* h_n,
+                            int32_t* h_counts, void* stream);
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char* fdas_last_error(void);
+
+/* --- host-only queries (no GPU needed) ------------------------------------ */
+
+/* FDAS_ABI_VERSION of the loaded library. */
+int32_t fdas_abi_version(void);
+
+/* FP64 taps of template z (the coefficients fdas_plan_create uploads, before
+ * rounding to FP32): taps[2*t] = Re h_z[d], taps[2*t+1] = Im h_z[d] for
+ * d = -L/2 + t, t in [0, L).  capacity counts complex taps; *n_taps gets L.
+ * |z| <= 64. */
+fdas_status fdas_template_taps(int32_t z, double* taps, int32_t capacity, int32_t* n_taps);
+
+/* Default thresholds T_k = Q^{-1}(k, p_fa), k = 1..n_harm, in FP64. */
+fdas_status fdas_thresholds(int32_t n_harm, double p_fa, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDAS_H */

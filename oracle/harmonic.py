@@ -40,29 +40,36 @@ def stretch_rows(k, z_max=42):
     return src + z_max
 
 
-def stretch_cols(k, n):
-    """Column that SP_k reads for every output column: floor(j / k)."""
-    return np.arange(n, dtype=np.int64) // k
+def stretch_cols(k, n, cols=None):
+    """Column that SP_k reads for every output column: floor(j / k).
+
+    ``cols`` restricts the output columns (default: all n)."""
+    j = np.arange(n, dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64)
+    return j // k
 
 
-def stretch_plane(plane, k):
-    """SP_k of Algorithm 1 (reading above): a gathered copy of the plane."""
+def stretch_plane(plane, k, cols=None):
+    """SP_k of Algorithm 1 (reading above): a gathered copy of the plane.
+
+    ``cols`` evaluates only those output columns (same definition)."""
     z_max = (plane.shape[0] - 1) // 2
     rows = stretch_rows(k, z_max)
-    cols = stretch_cols(k, plane.shape[1])
-    return plane[rows][:, cols]
+    src = stretch_cols(k, plane.shape[1], cols)
+    return plane[rows][:, src]
 
 
-def harmonic_planes(plane, n_harm=8):
+def harmonic_planes(plane, n_harm=8, cols=None):
     """Yield (k, HP_k) for k = 1..n_harm in the plane's own dtype.
 
     The sum is formed in k order, one rounding per step, exactly as
     HP_k = HP_{k-1} + SP_k; with a float32 plane this is the FP32 twin that a
     GPU kernel summing in the same order must reproduce bit for bit.
+    ``cols`` evaluates only those output columns.
     """
-    hp = np.zeros_like(plane)
+    ncols = plane.shape[1] if cols is None else len(cols)
+    hp = np.zeros((plane.shape[0], ncols), dtype=plane.dtype)
     for k in range(1, n_harm + 1):
-        hp = hp + stretch_plane(plane, k)
+        hp = hp + stretch_plane(plane, k, cols)
         yield k, hp
 
 
@@ -77,29 +84,32 @@ def threshold_array(n_harm=8, z_max=42, p_fa=1e-6):
     return np.repeat(t[:, None], 2 * z_max + 1, axis=1)
 
 
-def candidates(plane, n_harm=8, ta=None, p_fa=1e-6, top_k=0):
+def candidates(plane, n_harm=8, ta=None, p_fa=1e-6, top_k=0, cols=None):
     """Candidate list of Algorithm 1 as a CAND_DTYPE array in (k, i, j) order.
 
     plane: FOP (rows = templates, columns = bins), float64 or float32.  With a
     float32 plane the sums and the comparisons are done in float32 (TA rounded
-    to float32), which is the arithmetic of the GPU kernel.
+    to float32), which is the arithmetic of the GPU kernel.  ``cols`` (an
+    increasing array of output columns) restricts detection to those columns.
     """
+    colidx = np.arange(plane.shape[1], dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64)
     z_max = (plane.shape[0] - 1) // 2
     if ta is None:
         ta = threshold_array(n_harm, z_max, p_fa)
     ta = np.asarray(ta, dtype=plane.dtype)
     out = []
-    for k, hp in harmonic_planes(plane, n_harm):
-        rows, cols = np.nonzero(hp > ta[k - 1][:, None])
-        pw = hp[rows, cols].astype(np.float64)
+    for k, hp in harmonic_planes(plane, n_harm, cols):
+        rows, cc = np.nonzero(hp > ta[k - 1][:, None])
+        cols_k = colidx[cc]
+        pw = hp[rows, cc].astype(np.float64)
         if top_k and rows.size > top_k:
             # highest power first, ties by (i, j) ascending
-            order = np.lexsort((cols, rows, -pw))[:top_k]
-            rows, cols, pw = rows[order], cols[order], pw[order]
+            order = np.lexsort((cols_k, rows, -pw))[:top_k]
+            rows, cols_k, pw = rows[order], cols_k[order], pw[order]
         rec = np.empty(rows.size, dtype=CAND_DTYPE)
         rec["harm"] = k
         rec["z"] = rows - z_max
-        rec["r"] = cols
+        rec["r"] = cols_k
         rec["power"] = pw
         out.append(rec)
     allc = np.concatenate(out) if out else np.empty(0, dtype=CAND_DTYPE)
@@ -112,7 +122,7 @@ def plane_counts(cands, n_harm=8):
     return np.bincount(cands["harm"] - 1, minlength=n_harm).astype(np.int64)
 
 
-def guard_cells(plane, n_harm=8, ta=None, p_fa=1e-6, rel=1e-4):
+def guard_cells(plane, n_harm=8, ta=None, p_fa=1e-6, rel=1e-4, cols=None):
     """Cells whose FP64 harmonic sum lies within rel*T of the threshold.
 
     Returned as a set of (k, z, r).  A correct FP32 implementation may report
@@ -122,10 +132,11 @@ def guard_cells(plane, n_harm=8, ta=None, p_fa=1e-6, rel=1e-4):
     if ta is None:
         ta = threshold_array(n_harm, z_max, p_fa)
     ta = np.asarray(ta, dtype=np.float64)
+    colidx = np.arange(plane.shape[1], dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64)
     out = set()
-    for k, hp in harmonic_planes(np.asarray(plane, dtype=np.float64), n_harm):
+    for k, hp in harmonic_planes(np.asarray(plane, dtype=np.float64), n_harm, cols):
         t = ta[k - 1][:, None]
-        rows, cols = np.nonzero(np.abs(hp - t) <= rel * t)
-        out.update((k, int(r) - z_max, int(c)) for r, c in zip(rows, cols))
+        rows, cc = np.nonzero(np.abs(hp - t) <= rel * t)
+        out.update((k, int(r) - z_max, int(colidx[c])) for r, c in zip(rows, cc))
     return out
 

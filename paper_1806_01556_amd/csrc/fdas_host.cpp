@@ -1,0 +1,312 @@
+// libfdas host side: plan creation, argument validation, kernel launches and
+// candidate readback behind the C ABI of include/fdas.h.
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fdas_internal.h"
+
+struct fdas_plan {
+  fdas_plan_desc desc;
+  int device = 0;
+  int rows = 0;          // 2*z_max + 1
+  int L_max = 0;         // taps of the longest template
+  fdas::OlsGeom geom{};  // overlap-save chunk geometry
+  int tpg = 0;           // templates per workgroup (overlap-save)
+  float2* d_H = nullptr;    // [rows][C] template spectra
+  float2* d_tw1 = nullptr;  // [16][256]
+  float2* d_tw2 = nullptr;  // [16][16]
+  float* d_ta = nullptr;    // [n_harm][rows] default thresholds
+  std::vector<float> h_ta;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+fdas_status fail(fdas_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+fdas_status fail(fdas_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+fdas_status ok() {
+  g_err.clear();
+  return FDAS_OK;
+}
+
+fdas_status hip_fail(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) return fail(FDAS_ERR_OUT_OF_MEMORY, "%s: %s", what, hipGetErrorString(e));
+  return fail(FDAS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Make the plan's device current for the duration of a call.
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  hipError_t err = hipSuccess;
+  explicit DeviceGuard(int dev) {
+    err = hipGetDevice(&prev);
+    if (err == hipSuccess && prev != dev) {
+      err = hipSetDevice(dev);
+      changed = err == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+void free_plan(fdas_plan* p) {
+  if (!p) return;
+  if (p->d_H) (void)hipFree(p->d_H);
+  if (p->d_tw1) (void)hipFree(p->d_tw1);
+  if (p->d_tw2) (void)hipFree(p->d_tw2);
+  if (p->d_ta) (void)hipFree(p->d_ta);
+  delete p;
+}
+
+template <typename T>
+hipError_t upload(T** dst, const void* src, size_t bytes) {
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), bytes);
+  if (e != hipSuccess) {
+    *dst = nullptr;
+    return e;
+  }
+  return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+}
+
+fdas_status check_fop_args(const fdas_plan* p, const void* fop, int64_t n, int64_t ld) {
+  if (!fop) return fail(FDAS_ERR_INVALID_ARG, "FOP pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(fop) % 16 != 0) return fail(FDAS_ERR_INVALID_ARG, "FOP pointer must be 16-byte aligned");
+  if (n < 1 || n > p->desc.n_max)
+    return fail(FDAS_ERR_INVALID_ARG, "n = %lld outside [1, n_max = %lld]", (long long)n, (long long)p->desc.n_max);
+  if (ld < n) return fail(FDAS_ERR_INVALID_ARG, "ld = %lld < n = %lld", (long long)ld, (long long)n);
+  if (ld % 4 != 0) return fail(FDAS_ERR_INVALID_ARG, "ld = %lld is not a multiple of 4", (long long)ld);
+  return FDAS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fdas_plan_desc_default(fdas_plan_desc* d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->struct_size = (int32_t)sizeof(fdas_plan_desc);
+  d->z_max = 42;
+  d->n_max = (int64_t)1 << 22;
+  d->n_harm = 8;
+  d->cand_capacity = 65536;
+  d->p_fa = 1e-6;
+  d->top_k = 0;
+  d->method = FDAS_CONV_AUTO;
+  d->precision = FDAS_PREC_FP32;
+  d->hsum_index = FDAS_HSUM_STRETCH;
+  d->ols_chunk = 0;
+  d->device = 0;
+}
+
+const char* fdas_last_error(void) { return g_err.c_str(); }
+
+int32_t fdas_abi_version(void) { return FDAS_ABI_VERSION; }
+
+fdas_status fdas_template_taps(int32_t z, double* taps, int32_t capacity, int32_t* n_taps) {
+  if (z < -64 || z > 64) return fail(FDAS_ERR_INVALID_ARG, "|z| = %d > 64", (int)z);
+  const int L = fdas::tap_count(z);
+  if (n_taps) *n_taps = L;
+  if (!taps) return fail(FDAS_ERR_INVALID_ARG, "taps pointer is NULL");
+  if (capacity < L) return fail(FDAS_ERR_INVALID_ARG, "capacity %d < %d taps", (int)capacity, L);
+  std::vector<std::complex<double>> h;
+  fdas::template_taps(z, h);
+  for (int t = 0; t < L; ++t) {
+    taps[2 * t] = h[t].real();
+    taps[2 * t + 1] = h[t].imag();
+  }
+  return ok();
+}
+
+fdas_status fdas_thresholds(int32_t n_harm, double p_fa, double* out) {
+  if (n_harm < 1 || n_harm > 8) return fail(FDAS_ERR_INVALID_ARG, "n_harm = %d outside [1, 8]", (int)n_harm);
+  if (!(p_fa > 0.0 && p_fa < 1.0)) return fail(FDAS_ERR_INVALID_ARG, "p_fa must lie in (0, 1)");
+  if (!out) return fail(FDAS_ERR_INVALID_ARG, "out pointer is NULL");
+  for (int k = 1; k <= n_harm; ++k) out[k - 1] = fdas::erlang_threshold(k, p_fa);
+  return ok();
+}
+
+fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
+  if (!out) return fail(FDAS_ERR_INVALID_ARG, "out pointer is NULL");
+  *out = nullptr;
+  if (!desc) return fail(FDAS_ERR_INVALID_ARG, "descriptor is NULL");
+  if (desc->struct_size != (int32_t)sizeof(fdas_plan_desc))
+    return fail(FDAS_ERR_INVALID_ARG, "struct_size %d != %d (header/library mismatch)", (int)desc->struct_size,
+                (int)sizeof(fdas_plan_desc));
+  if (desc->z_max < 0 || desc->z_max > 64) return fail(FDAS_ERR_INVALID_ARG, "z_max = %d outside [0, 64]", (int)desc->z_max);
+  if (desc->n_max < 1 || desc->n_max > ((int64_t)1 << 30))
+    return fail(FDAS_ERR_INVALID_ARG, "n_max = %lld outside [1, 2^30]", (long long)desc->n_max);
+  if (desc->n_harm < 1 || desc->n_harm > 8) return fail(FDAS_ERR_INVALID_ARG, "n_harm = %d outside [1, 8]", (int)desc->n_harm);
+  if (desc->cand_capacity < 1 || desc->cand_capacity > (1 << 26))
+    return fail(FDAS_ERR_INVALID_ARG, "cand_capacity = %d outside [1, 2^26]", (int)desc->cand_capacity);
+  if (!(desc->p_fa > 0.0 && desc->p_fa < 1.0)) return fail(FDAS_ERR_INVALID_ARG, "p_fa must lie in (0, 1)");
+  if (desc->top_k < 0) return fail(FDAS_ERR_INVALID_ARG, "top_k < 0");
+  if (desc->method != FDAS_CONV_AUTO && desc->method != FDAS_CONV_OLS_FFT && desc->method != FDAS_CONV_DIRECT)
+    return fail(FDAS_ERR_INVALID_ARG, "unknown method %d", (int)desc->method);
+  if (desc->method == FDAS_CONV_DIRECT)
+    return fail(FDAS_ERR_UNSUPPORTED, "the direct method is not built in this library");
+  if (desc->precision != FDAS_PREC_FP32) return fail(FDAS_ERR_UNSUPPORTED, "precision %d is not built", (int)desc->precision);
+  if (desc->hsum_index != FDAS_HSUM_STRETCH) return fail(FDAS_ERR_UNSUPPORTED, "hsum_index %d is not built", (int)desc->hsum_index);
+  if (desc->ols_chunk != 0 && desc->ols_chunk != fdas::kOlsC)
+    return fail(FDAS_ERR_UNSUPPORTED, "ols_chunk %d: only %d is built", (int)desc->ols_chunk, fdas::kOlsC);
+
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev < 1) return fail(FDAS_ERR_NO_DEVICE, "no HIP device (%s)", hipGetErrorString(e));
+  if (desc->device < 0 || desc->device >= ndev)
+    return fail(FDAS_ERR_NO_DEVICE, "device %d outside [0, %d)", (int)desc->device, ndev);
+
+  fdas_plan* p = new (std::nothrow) fdas_plan();
+  if (!p) return fail(FDAS_ERR_OUT_OF_MEMORY, "host allocation of the plan failed");
+  p->desc = *desc;
+  p->device = desc->device;
+  p->rows = 2 * desc->z_max + 1;
+  p->L_max = fdas::tap_count(desc->z_max);
+  p->geom.C = fdas::kOlsC;
+  p->geom.P = p->L_max / 2;
+  p->geom.V = p->geom.C - (p->L_max - 1);
+  p->tpg = 17;
+
+  DeviceGuard dg(p->device);
+  if (dg.err != hipSuccess) {
+    free_plan(p);
+    return hip_fail(dg.err, "hipSetDevice");
+  }
+
+  std::vector<std::vector<std::complex<double>>> bank;
+  fdas::template_bank(desc->z_max, bank);
+  std::vector<float> H, tw1, tw2;
+  fdas::ols_spectra(bank, p->geom.C, p->geom.P, H);
+  fdas::fft_twiddles(tw1, tw2);
+  p->h_ta.resize((size_t)desc->n_harm * p->rows);
+  for (int k = 1; k <= desc->n_harm; ++k) {
+    const float t = (float)fdas::erlang_threshold(k, desc->p_fa);
+    for (int r = 0; r < p->rows; ++r) p->h_ta[(size_t)(k - 1) * p->rows + r] = t;
+  }
+
+  if ((e = upload(&p->d_H, H.data(), H.size() * sizeof(float))) != hipSuccess ||
+      (e = upload(&p->d_tw1, tw1.data(), tw1.size() * sizeof(float))) != hipSuccess ||
+      (e = upload(&p->d_tw2, tw2.data(), tw2.size() * sizeof(float))) != hipSuccess ||
+      (e = upload(&p->d_ta, p->h_ta.data(), p->h_ta.size() * sizeof(float))) != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "uploading plan tables");
+  }
+  *out = p;
+  return ok();
+}
+
+fdas_status fdas_plan_destroy(fdas_plan* plan) {
+  if (!plan) return ok();
+  DeviceGuard dg(plan->device);
+  (void)hipDeviceSynchronize();
+  free_plan(plan);
+  return ok();
+}
+
+fdas_status fdas_convolve(fdas_plan* p, const void* d_spectrum, int64_t n, float* d_fop, int64_t ld, void* stream) {
+  if (!p) return fail(FDAS_ERR_INVALID_ARG, "plan is NULL");
+  if (!d_spectrum) return fail(FDAS_ERR_INVALID_ARG, "spectrum pointer is NULL");
+  if (reinterpret_cast<uintptr_t>(d_spectrum) % 8 != 0)
+    return fail(FDAS_ERR_INVALID_ARG, "spectrum pointer must be 8-byte aligned");
+  fdas_status st = check_fop_args(p, d_fop, n, ld);
+  if (st != FDAS_OK) return st;
+  DeviceGuard dg(p->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  hipError_t e = fdas::launch_ols_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1,
+                                       p->d_tw2, p->rows, p->tpg, p->geom, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "launching the overlap-save convolution");
+  return ok();
+}
+
+fdas_status fdas_harmonic_sum(fdas_plan* p, const float* d_fop, int64_t n, int64_t ld, const float* d_ta,
+                              fdas_cand* d_cands, int32_t* d_counts, void* stream) {
+  if (!p) return fail(FDAS_ERR_INVALID_ARG, "plan is NULL");
+  fdas_status st = check_fop_args(p, d_fop, n, ld);
+  if (st != FDAS_OK) return st;
+  if (!d_cands) return fail(FDAS_ERR_INVALID_ARG, "candidate buffer is NULL");
+  if (reinterpret_cast<uintptr_t>(d_cands) % 16 != 0)
+    return fail(FDAS_ERR_INVALID_ARG, "candidate buffer must be 16-byte aligned");
+  if (!d_counts) return fail(FDAS_ERR_INVALID_ARG, "count buffer is NULL");
+  DeviceGuard dg(p->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = fdas::launch_fill_i32(d_counts, p->desc.n_harm, 0, s);
+  if (e != hipSuccess) return hip_fail(e, "clearing the candidate counts");
+  e = fdas::launch_harmsum(d_fop, n, ld, p->desc.z_max, p->desc.n_harm, d_ta ? d_ta : p->d_ta, d_cands,
+                           p->desc.cand_capacity, d_counts, s);
+  if (e != hipSuccess) return hip_fail(e, "launching the harmonic sum");
+  return ok();
+}
+
+fdas_status fdas_candidates(fdas_plan* p, const fdas_cand* d_cands, const int32_t* d_counts, fdas_cand* h_out,
+                            int64_t h_capacity, int64_t* h_n, int32_t* h_counts, void* stream) {
+  if (!p) return fail(FDAS_ERR_INVALID_ARG, "plan is NULL");
+  if (!d_cands || !d_counts) return fail(FDAS_ERR_INVALID_ARG, "device candidate buffers are NULL");
+  if (!h_n) return fail(FDAS_ERR_INVALID_ARG, "h_n is NULL");
+  if (h_capacity < 0 || (h_capacity > 0 && !h_out)) return fail(FDAS_ERR_INVALID_ARG, "bad host output buffer");
+  *h_n = 0;
+  DeviceGuard dg(p->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nh = p->desc.n_harm;
+  const int cap = p->desc.cand_capacity;
+  std::vector<int32_t> counts(nh, 0);
+  hipError_t e = hipMemcpyAsync(counts.data(), d_counts, nh * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading candidate counts");
+  if (h_counts) std::copy(counts.begin(), counts.end(), h_counts);
+  bool overflow = false;
+  std::vector<fdas_cand> all;
+  for (int k = 0; k < nh; ++k) {
+    const int c = counts[k];
+    if (c < 0) return fail(FDAS_ERR_DEVICE, "negative candidate count");
+    const int take = std::min(c, cap);
+    if (c > cap) overflow = true;
+    std::vector<fdas_cand> v(take);
+    if (take > 0) {
+      e = hipMemcpyAsync(v.data(), d_cands + (size_t)k * cap, take * sizeof(fdas_cand), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) return hip_fail(e, "reading candidates");
+    }
+    if (p->desc.top_k > 0 && (int)v.size() > p->desc.top_k) {
+      std::sort(v.begin(), v.end(), [](const fdas_cand& a, const fdas_cand& b) {
+        if (a.power != b.power) return a.power > b.power;
+        if (a.z != b.z) return a.z < b.z;
+        return a.r < b.r;
+      });
+      v.resize(p->desc.top_k);
+    }
+    all.insert(all.end(), v.begin(), v.end());
+  }
+  std::sort(all.begin(), all.end(), [](const fdas_cand& a, const fdas_cand& b) {
+    if (a.harm != b.harm) return a.harm < b.harm;
+    if (a.z != b.z) return a.z < b.z;
+    return a.r < b.r;
+  });
+  const int64_t nw = std::min<int64_t>((int64_t)all.size(), h_capacity);
+  if (nw > 0) std::memcpy(h_out, all.data(), (size_t)nw * sizeof(fdas_cand));
+  *h_n = nw;
+  if (overflow) return fail(FDAS_ERR_CAPACITY, "a device candidate list overflowed (counts are exact)");
+  if (nw < (int64_t)all.size()) return fail(FDAS_ERR_CAPACITY, "h_capacity %lld < %zu candidates", (long long)h_capacity, all.size());
+  return ok();
+}
+
+}  // extern "C"

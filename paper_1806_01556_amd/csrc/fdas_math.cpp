@@ -1,0 +1,222 @@
+// Host-side FP64 arithmetic of plan creation: acceleration templates, their
+// overlap-save spectra, FFT twiddle tables and detection thresholds.
+//
+// Templates.  FDAS correlates the spectrum with the conjugate Fourier response
+// of a signal whose frequency drifts by z bins over the observation (the paper
+// names the Ransom et al. correlation technique and gives 85 filters of up to
+// ~400 taps, Section 1 and Table 1, but prints no coefficients).  Here
+//   A(q, z) = integral_0^1 exp(i*pi*(z*u^2 + (2q - z)*u)) du,
+// evaluated by composite Gauss-Legendre quadrature (nodes from Newton's method
+// on the Legendre recurrence), and
+//   h_z[d] = conj(A(-d, z)) / sqrt(E_z),  E_z = sum_d |A(-d, z)|^2,
+//   d in [-L/2, L/2 - 1],  L(z) = 2*(8 + ceil(4.5*|z|)).
+// The integrand's phase turns at most pi*(|z| + 2|q|) radians per unit u; the
+// panel count keeps that below ~5.4 rad per 16-node panel, where the
+// Gauss-Legendre remainder is far below double rounding.
+//
+// Thresholds.  HP_k of unit-mean exponential noise is Gamma(k, 1); its survival
+// function for integer k is exp(-T) * sum_{n<k} T^n / n!.  T_k solves
+// survival = p_fa (bisection, then Newton on the logarithm).
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <thread>
+#include <vector>
+
+#include "fdas_internal.h"
+
+namespace fdas {
+
+using cd = std::complex<double>;
+
+int tap_count(int z) {
+  const int az = z < 0 ? -z : z;
+  return 2 * (8 + (9 * az + 1) / 2);
+}
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double pi = M_PI;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double r = std::cos(pi * (i + 0.75) / (n + 0.5));
+    double dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = r;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * r * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_n(r), p0 = P_{n-1}(r)
+      dp = n * (r * p1 - p0) / (r * r - 1.0);
+      const double dr = p1 / dp;
+      r -= dr;
+      if (std::fabs(dr) < 1e-16) break;
+    }
+    // recompute the derivative at the converged root
+    double p0 = 1.0, p1 = r;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * r * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    dp = n * (r * p1 - p0) / (r * r - 1.0);
+    x[i] = -r;
+    x[n - 1 - i] = r;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - r * r) * dp * dp);
+  }
+}
+
+// exp(2*pi*i*t) for a real t, with t reduced to [0, 1) first.
+static inline cd expi2pi(double t) {
+  t -= std::floor(t);
+  const double a = 2.0 * M_PI * t;
+  return cd(std::cos(a), std::sin(a));
+}
+
+void template_taps(int z, std::vector<cd>& h) {
+  const int L = tap_count(z);
+  const int half = L / 2;
+  // taps need A(q, z) for q = -d, d in [-half, half-1]  ->  q in [1-half, half]
+  const int q_lo = 1 - half, q_hi = half;
+  const double max_rate = M_PI * (std::fabs((double)z) + 2.0 * std::max(std::abs(q_lo), std::abs(q_hi)));
+  const int order = 16;
+  int panels = (int)std::ceil(max_rate / 5.0);
+  panels = std::max(panels, 16);
+  std::vector<double> gx, gw;
+  gauss_legendre(order, gx, gw);
+  const int nn = panels * order;
+  std::vector<double> u(nn);
+  std::vector<cd> g(nn), step(nn), cur(nn);
+  for (int p = 0; p < panels; ++p) {
+    const double a = (double)p / panels, b = (double)(p + 1) / panels;
+    for (int m = 0; m < order; ++m) {
+      const double uu = 0.5 * (b - a) * gx[m] + 0.5 * (a + b);
+      const double ww = 0.5 * (b - a) * gw[m];
+      const int idx = p * order + m;
+      u[idx] = uu;
+      // exp(i*pi*z*(u^2 - u)) carries the drift; exp(2*pi*i*q*u) the offset.
+      g[idx] = ww * expi2pi(0.5 * z * (uu * uu - uu));
+      step[idx] = expi2pi(uu);
+    }
+  }
+  std::vector<cd> A(q_hi - q_lo + 1);
+  for (int q = q_lo; q <= q_hi; ++q) {
+    const int k = q - q_lo;
+    if (k % 32 == 0) {
+      for (int m = 0; m < nn; ++m) cur[m] = expi2pi((double)q * u[m]);
+    }
+    cd acc(0.0, 0.0);
+    for (int m = 0; m < nn; ++m) {
+      acc += g[m] * cur[m];
+      cur[m] *= step[m];
+    }
+    A[k] = acc;
+  }
+  double energy = 0.0;
+  for (const cd& a : A) energy += std::norm(a);
+  const double inv = 1.0 / std::sqrt(energy);
+  h.assign(L, cd(0.0, 0.0));
+  for (int t = 0; t < L; ++t) {
+    const int d = t - half;
+    const int q = -d;
+    h[t] = std::conj(A[q - q_lo]) * inv;
+  }
+}
+
+void template_bank(int z_max, std::vector<std::vector<cd>>& bank) {
+  const int rows = 2 * z_max + 1;
+  bank.assign(rows, {});
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned w = 0; w < hw; ++w) {
+    th.emplace_back([&, w]() {
+      for (int r = (int)w; r < rows; r += (int)hw) template_taps(r - z_max, bank[r]);
+    });
+  }
+  for (auto& t : th) t.join();
+}
+
+void ols_spectra(const std::vector<std::vector<cd>>& bank, int C, int P, std::vector<float>& out) {
+  // g[t] = h[t - P] on t in [P - L/2, P + L/2 - 1];  H[k] = (1/C) sum_t g[t] e^{+2 pi i t k / C}.
+  const int rows = (int)bank.size();
+  out.assign((size_t)rows * C * 2, 0.0f);
+  std::vector<cd> tw(C);
+  for (int m = 0; m < C; ++m) tw[m] = expi2pi((double)m / C);
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned w = 0; w < hw; ++w) {
+    th.emplace_back([&, w]() {
+      for (int r = (int)w; r < rows; r += (int)hw) {
+        const std::vector<cd>& h = bank[r];
+        const int L = (int)h.size();
+        const int t0 = P - L / 2;
+        for (int k = 0; k < C; ++k) {
+          cd acc(0.0, 0.0);
+          for (int s = 0; s < L; ++s) {
+            const long long t = t0 + s;
+            acc += h[s] * tw[(size_t)((t * k) % C)];
+          }
+          acc /= (double)C;
+          out[((size_t)r * C + k) * 2 + 0] = (float)acc.real();
+          out[((size_t)r * C + k) * 2 + 1] = (float)acc.imag();
+        }
+      }
+    });
+  }
+  for (auto& t : th) t.join();
+}
+
+void fft_twiddles(std::vector<float>& tw1, std::vector<float>& tw2) {
+  // tw1[nb][t] = e^{+2 pi i nb t / 4096} (nb < 16, t < 256); tw2[q][c] = e^{+2 pi i q c / 256}.
+  tw1.assign(16 * 256 * 2, 0.0f);
+  tw2.assign(16 * 16 * 2, 0.0f);
+  for (int nb = 0; nb < 16; ++nb)
+    for (int t = 0; t < 256; ++t) {
+      const cd w = expi2pi((double)(nb * t) / 4096.0);
+      tw1[(nb * 256 + t) * 2 + 0] = (float)w.real();
+      tw1[(nb * 256 + t) * 2 + 1] = (float)w.imag();
+    }
+  for (int q = 0; q < 16; ++q)
+    for (int c = 0; c < 16; ++c) {
+      const cd w = expi2pi((double)(q * c) / 256.0);
+      tw2[(q * 16 + c) * 2 + 0] = (float)w.real();
+      tw2[(q * 16 + c) * 2 + 1] = (float)w.imag();
+    }
+}
+
+static double log_survival(int k, double t) {
+  double term = 1.0, acc = 1.0;
+  for (int n = 1; n < k; ++n) {
+    term *= t / n;
+    acc += term;
+  }
+  return -t + std::log(acc);
+}
+
+double erlang_threshold(int k, double p_fa) {
+  const double target = std::log(p_fa);
+  double lo = 0.0, hi = 1.0;
+  while (log_survival(k, hi) > target) hi *= 2.0;
+  for (int it = 0; it < 200 && hi - lo > 1e-13 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (log_survival(k, mid) > target) lo = mid; else hi = mid;
+  }
+  double t = 0.5 * (lo + hi);
+  for (int it = 0; it < 4; ++it) {
+    // d/dt log S = -(t^{k-1}/(k-1)!) / sum_{n<k} t^n/n!
+    double term = 1.0, acc = 1.0;
+    for (int n = 1; n < k; ++n) {
+      term *= t / n;
+      acc += term;
+    }
+    const double dlog = -term / acc;
+    const double f = log_survival(k, t) - target;
+    t -= f / dlog;
+  }
+  return t;
+}
+
+}  // namespace fdas

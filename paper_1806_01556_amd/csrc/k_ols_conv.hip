@@ -1,0 +1,226 @@
+// Overlap-save FFT correlation of a complex spectrum with every acceleration
+// template, fused with the power and the discard of the overlap
+// (Section 2.1.2 overlap-save FDFIR, eq. (2); power as in Section 2.2).
+//
+// One workgroup = one chunk of C = 4096 input bins and a group of templates.
+//   chunk c covers outputs j in [c*V, c*V + V), V = C - (L_max - 1), and reads
+//   X[c*V - P + t], t in [0, C), P = L_max/2, zero outside [0, n).
+//   F = FFT(chunk) once (shared by all templates of the group, as the
+//   area-efficient AOLS design of Section 2.1.3 transforms the input once),
+//   then per template: y = IFFT(F * H_z), |y|^2 of the first V outputs -> FOP.
+//   H_z = (1/C) * sum_t g_z[t] e^{+2 pi i t k / C} with g_z the template placed
+//   at t = P + d, so y[s] = sum_d X[c*V + s + d] h_z[d] (centred correlation).
+//
+// The 4096-point FFT runs in three radix-16 passes, 256 threads x 16 points:
+//   pass 1: thread t transforms x[t + 256 r] over r (16 points in registers),
+//           twiddle w4096^(nb*t), write to LDS buffer 1;
+//   pass 2: thread (nb, c) transforms the 16 values c + 16 d over d,
+//           twiddle w256^(q*c), write to LDS buffer 2;
+//   pass 3: thread (q, nb) transforms over c and ends holding output
+//           y[t + 256 p] in register p -- the same layout as the input, so
+//           the forward result F stays in registers for every template.
+// LDS strides (272 complex per row) and the XOR swizzle of buffer 2 make every
+// LDS access of a half-wave hit distinct banks.  No packed-FP32 instructions
+// are written here (the build disables them).
+
+#include "fdas_internal.h"
+
+namespace fdas {
+namespace {
+
+constexpr int NT = kOlsThreads;   // 256
+constexpr int RS = 272;           // LDS row stride, complex elements
+
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+__device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
+  return make_float2(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+// multiply by w^s with w the stored (positive-exponent) twiddle: S = +1 -> w, S = -1 -> conj(w)
+template <int S>
+__device__ __forceinline__ float2 ctw(float2 a, float2 w) {
+  if constexpr (S > 0) return cmul(a, w); else return cmulc(a, w);
+}
+
+// 4-point DFT with exponent sign S, in place: (a, b, c, d) -> (X0, X1, X2, X3).
+template <int S>
+__device__ __forceinline__ void dft4(float2& a, float2& b, float2& c, float2& d) {
+  const float2 t0 = cadd(a, c), t1 = csub(a, c), t2 = cadd(b, d), t3 = csub(b, d);
+  // S*i*t3
+  const float2 it3 = S > 0 ? make_float2(-t3.y, t3.x) : make_float2(t3.y, -t3.x);
+  a = cadd(t0, t2);
+  c = csub(t0, t2);
+  b = cadd(t1, it3);
+  d = csub(t1, it3);
+}
+
+// Multiply by w16^(S*e), e in {1, 2, 3, 4, 6, 9} (the internal twiddles of a 4x4 FFT).
+template <int S, int E>
+__device__ __forceinline__ float2 tw16(float2 v) {
+  constexpr float R2 = 0.70710678118654752440f;
+  constexpr float C1 = 0.92387953251128675613f;  // cos(pi/8)
+  constexpr float S1 = 0.38268343236508977173f;  // sin(pi/8)
+  if constexpr (E == 0) {
+    return v;
+  } else if constexpr (E == 4) {  // S*i
+    return S > 0 ? make_float2(-v.y, v.x) : make_float2(v.y, -v.x);
+  } else if constexpr (E == 2) {  // (1 + S i)/sqrt2
+    return S > 0 ? make_float2((v.x - v.y) * R2, (v.y + v.x) * R2)
+                 : make_float2((v.x + v.y) * R2, (v.y - v.x) * R2);
+  } else if constexpr (E == 6) {  // (-1 + S i)/sqrt2
+    return S > 0 ? make_float2((-v.x - v.y) * R2, (v.x - v.y) * R2)
+                 : make_float2((v.y - v.x) * R2, (-v.y - v.x) * R2);
+  } else {
+    // e in {1, 3, 9}: cos/sin of 2*pi*e/16
+    constexpr float c = E == 1 ? C1 : (E == 3 ? S1 : -C1);
+    constexpr float s0 = E == 1 ? S1 : (E == 3 ? C1 : -S1);
+    constexpr float s = S > 0 ? s0 : -s0;
+    return make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+  }
+}
+
+// 16-point DFT, exponent sign S, in registers.  Afterwards v[p] holds output
+// index perm16(p) = (p >> 2) + 4 * (p & 3) (digit reversal, an involution).
+template <int S>
+__device__ __forceinline__ void fft16(float2 (&v)[16]) {
+#pragma unroll
+  for (int m0 = 0; m0 < 4; ++m0) dft4<S>(v[m0], v[4 + m0], v[8 + m0], v[12 + m0]);
+  // v[4*k0 + m0] *= w16^(S*m0*k0)
+  v[5] = tw16<S, 1>(v[5]);
+  v[6] = tw16<S, 2>(v[6]);
+  v[7] = tw16<S, 3>(v[7]);
+  v[9] = tw16<S, 2>(v[9]);
+  v[10] = tw16<S, 4>(v[10]);
+  v[11] = tw16<S, 6>(v[11]);
+  v[13] = tw16<S, 3>(v[13]);
+  v[14] = tw16<S, 6>(v[14]);
+  v[15] = tw16<S, 9>(v[15]);
+#pragma unroll
+  for (int k0 = 0; k0 < 4; ++k0) dft4<S>(v[4 * k0 + 0], v[4 * k0 + 1], v[4 * k0 + 2], v[4 * k0 + 3]);
+}
+
+__host__ __device__ constexpr int perm16(int p) { return (p >> 2) + 4 * (p & 3); }
+
+// 4096-point DFT with exponent sign S over the workgroup.
+// In:  v[r] = x[tid + 256 r].  Out: v[r] = X[tid + 256 r].
+// tw1[nb-1] = w4096^(nb*tid), tw2[q-1] = w256^(q*(tid & 15)) (positive exponent).
+template <int S>
+__device__ __forceinline__ void fft4096(float2 (&v)[16], const float2 (&tw1)[15], const float2 (&tw2)[15],
+                                        float2* __restrict__ buf1, float2* __restrict__ buf2, int tid) {
+  // pass 1: over r, then twiddle by w4096^(nb*t); element (nb, t) -> buf1[nb*RS + t]
+  fft16<S>(v);
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int nb = perm16(p);
+    float2 a = v[p];
+    if (nb != 0) a = ctw<S>(a, tw1[nb - 1]);
+    buf1[nb * RS + tid] = a;
+  }
+  __syncthreads();
+  // pass 2: thread (nb2, c), transform over d of element (nb2, c + 16 d)
+  {
+    const int nb2 = tid >> 4, c = tid & 15;
+#pragma unroll
+    for (int d = 0; d < 16; ++d) v[d] = buf1[nb2 * RS + c + 16 * d];
+    fft16<S>(v);
+#pragma unroll
+    for (int p = 0; p < 16; ++p) {
+      const int q = perm16(p);
+      float2 a = v[p];
+      if (q != 0) a = ctw<S>(a, tw2[q - 1]);
+      buf2[q * RS + 16 * nb2 + (c ^ nb2)] = a;
+    }
+  }
+  __syncthreads();
+  // pass 3: thread (q3, nb3), transform over c
+  {
+    const int q3 = tid >> 4, nb3 = tid & 15;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) v[c] = buf2[q3 * RS + 16 * nb3 + (c ^ nb3)];
+    fft16<S>(v);
+  }
+  // v[p] now holds X[tid + 256 * perm16(p)]; restore natural register order.
+  float2 t[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) t[r] = v[perm16(r)];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = t[r];
+}
+
+__global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x, int64_t n,
+                                                    float* __restrict__ fop, int64_t ld,
+                                                    const float2* __restrict__ H,
+                                                    const float2* __restrict__ tw1tab,
+                                                    const float2* __restrict__ tw2tab, int rows,
+                                                    int tpg, int V, int P) {
+  __shared__ float2 buf1[16 * RS];
+  __shared__ float2 buf2[16 * RS];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * V;
+  const int z_lo = blockIdx.y * tpg;
+  const int z_hi = min(rows, z_lo + tpg);
+
+  float2 tw1[15], tw2[15];
+#pragma unroll
+  for (int k = 1; k < 16; ++k) {
+    tw1[k - 1] = tw1tab[k * 256 + tid];
+    tw2[k - 1] = tw2tab[k * 16 + (tid & 15)];
+  }
+
+  float2 v[16];
+  const int64_t in0 = base - P + tid;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t idx = in0 + 256 * r;
+    v[r] = (idx >= 0 && idx < n) ? x[idx] : make_float2(0.0f, 0.0f);
+  }
+  fft4096<-1>(v, tw1, tw2, buf1, buf2, tid);
+  float2 F[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) F[r] = v[r];
+
+  // outputs of this chunk that exist: s < V and base + s < n
+  const int64_t lim64 = n - base < (int64_t)V ? n - base : (int64_t)V;
+  const int lim = (int)lim64;
+
+  float2 hn[16];
+  {
+    const float2* Hz = H + (size_t)z_lo * kOlsC + tid;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) hn[r] = Hz[256 * r];
+  }
+  for (int z = z_lo; z < z_hi; ++z) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = cmul(F[r], hn[r]);
+    if (z + 1 < z_hi) {
+      const float2* Hz = H + (size_t)(z + 1) * kOlsC + tid;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) hn[r] = Hz[256 * r];
+    }
+    fft4096<1>(v, tw1, tw2, buf1, buf2, tid);
+    float* out = fop + (size_t)z * ld + base;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int s = tid + 256 * r;
+      if (s < lim) out[s] = v[r].x * v[r].x + v[r].y * v[r].y;
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
+                           const float2* tw1, const float2* tw2, int rows, int tpg, const OlsGeom& g,
+                           hipStream_t s) {
+  const int64_t chunks = (n + g.V - 1) / g.V;
+  const int groups = (rows + tpg - 1) / tpg;
+  dim3 grid((unsigned)chunks, (unsigned)groups);
+  hipLaunchKernelGGL(k_ols_conv, grid, dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, tpg, g.V, g.P);
+  return hipGetLastError();
+}
+
+}  // namespace fdas

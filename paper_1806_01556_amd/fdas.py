@@ -1,0 +1,258 @@
+"""Thin ctypes binding of libfdas (the C ABI in include/fdas.h).
+
+Argument marshalling only: every step of the hot path runs in the library's
+HIP kernels.  Device buffers are torch tensors (or raw integer device
+addresses); streams are torch streams or raw hipStream_t integers.  If the
+shared library is not built this module raises on first use -- there is no
+fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdas.so")
+
+# status codes
+OK, ERR_INVALID_ARG, ERR_NO_DEVICE, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_CAPACITY, ERR_UNSUPPORTED = range(7)
+STATUS_NAMES = {
+    0: "FDAS_OK", 1: "FDAS_ERR_INVALID_ARG", 2: "FDAS_ERR_NO_DEVICE", 3: "FDAS_ERR_OUT_OF_MEMORY",
+    4: "FDAS_ERR_DEVICE", 5: "FDAS_ERR_CAPACITY", 6: "FDAS_ERR_UNSUPPORTED",
+}
+CONV_AUTO, CONV_OLS_FFT, CONV_DIRECT = 0, 1, 2
+PREC_FP32 = 0
+HSUM_STRETCH = 0
+
+#: symbols declared in include/fdas.h
+EXPORTED = (
+    "fdas_plan_desc_default", "fdas_plan_create", "fdas_plan_destroy", "fdas_convolve",
+    "fdas_harmonic_sum", "fdas_candidates", "fdas_last_error", "fdas_abi_version",
+    "fdas_template_taps", "fdas_thresholds",
+)
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_int32),
+        ("z_max", ctypes.c_int32),
+        ("n_max", ctypes.c_int64),
+        ("n_harm", ctypes.c_int32),
+        ("cand_capacity", ctypes.c_int32),
+        ("p_fa", ctypes.c_double),
+        ("top_k", ctypes.c_int32),
+        ("method", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("hsum_index", ctypes.c_int32),
+        ("ols_chunk", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+    ]
+
+
+class Cand(ctypes.Structure):
+    _fields_ = [("harm", ctypes.c_int32), ("z", ctypes.c_int32), ("r", ctypes.c_int32), ("power", ctypes.c_float)]
+
+
+CAND_DTYPE = np.dtype([("harm", np.int32), ("z", np.int32), ("r", np.int32), ("power", np.float32)])
+
+
+class FdasError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libfdas (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1806_01556_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    L.fdas_plan_desc_default.argtypes = [ctypes.POINTER(PlanDesc)]
+    L.fdas_plan_desc_default.restype = None
+    L.fdas_plan_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)]
+    L.fdas_plan_destroy.argtypes = [vp]
+    L.fdas_convolve.argtypes = [vp, vp, i64, vp, i64, vp]
+    L.fdas_harmonic_sum.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp]
+    L.fdas_candidates.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp, vp]
+    L.fdas_last_error.argtypes = []
+    L.fdas_last_error.restype = ctypes.c_char_p
+    L.fdas_abi_version.argtypes = []
+    L.fdas_abi_version.restype = i32
+    L.fdas_template_taps.argtypes = [i32, vp, i32, ctypes.POINTER(i32)]
+    L.fdas_thresholds.argtypes = [i32, dbl, vp]
+    for name in ("fdas_plan_create", "fdas_plan_destroy", "fdas_convolve", "fdas_harmonic_sum",
+                 "fdas_candidates", "fdas_template_taps", "fdas_thresholds"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def last_error():
+    return lib().fdas_last_error().decode()
+
+
+def _check(status):
+    if status != OK:
+        raise FdasError(status, last_error())
+
+
+def _ptr(x):
+    """Device/host address of a torch tensor, numpy array or integer (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if hasattr(x, "data_ptr"):
+        return x.data_ptr()
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    raise TypeError(f"cannot take the address of {type(x)}")
+
+
+def _stream(s):
+    if s is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            pass
+        return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def abi_version():
+    return lib().fdas_abi_version()
+
+
+def plan_desc_default(**overrides):
+    d = PlanDesc()
+    lib().fdas_plan_desc_default(ctypes.byref(d))
+    for k, v in overrides.items():
+        if not hasattr(d, k):
+            raise AttributeError(k)
+        setattr(d, k, v)
+    return d
+
+
+class Plan:
+    """Owns an fdas_plan*; destroy() (or the context manager) releases it."""
+
+    def __init__(self, handle, desc):
+        self.handle = handle
+        self.desc = desc
+        self.rows = 2 * desc.z_max + 1
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().fdas_plan_destroy(self.handle))
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+
+def plan_create(desc=None, **overrides):
+    if desc is None:
+        desc = plan_desc_default(**overrides)
+    h = ctypes.c_void_p()
+    _check(lib().fdas_plan_create(ctypes.byref(desc), ctypes.byref(h)))
+    return Plan(h.value, desc)
+
+
+def plan_destroy(plan):
+    plan.destroy()
+
+
+def convolve(plan, spectrum, fop, n=None, ld=None, stream=None):
+    """FOP[z + z_max, j] = |sum_d X[j+d] h_z[d]|^2 for j < n (asynchronous)."""
+    if n is None:
+        n = spectrum.shape[0]
+    if ld is None:
+        ld = fop.shape[1] if hasattr(fop, "shape") and len(fop.shape) == 2 else n
+    _check(lib().fdas_convolve(plan.handle, _ptr(spectrum), int(n), _ptr(fop), int(ld), _stream(stream)))
+
+
+def harmonic_sum(plan, fop, n, cands, counts, ta=None, ld=None, stream=None):
+    """Algorithm 1 over the FOP; appends cells above TA to cands, counts per plane (asynchronous)."""
+    if ld is None:
+        ld = fop.shape[1]
+    _check(lib().fdas_harmonic_sum(plan.handle, _ptr(fop), int(n), int(ld), _ptr(ta), _ptr(cands),
+                                   _ptr(counts), _stream(stream)))
+
+
+def candidates(plan, cands, counts, capacity=None, stream=None, allow_overflow=False):
+    """Ordered candidate records (numpy CAND_DTYPE) and the per-plane device counts."""
+    nh = plan.desc.n_harm
+    if capacity is None:
+        capacity = nh * plan.desc.cand_capacity
+    out = np.zeros(capacity, dtype=CAND_DTYPE)
+    hc = np.zeros(nh, dtype=np.int32)
+    nw = ctypes.c_int64(0)
+    st = lib().fdas_candidates(plan.handle, _ptr(cands), _ptr(counts), out.ctypes.data, int(capacity),
+                               ctypes.byref(nw), hc.ctypes.data, _stream(stream))
+    if st == ERR_CAPACITY and allow_overflow:
+        return out[: nw.value], hc
+    _check(st)
+    return out[: nw.value], hc
+
+
+def template_taps(z):
+    """FP64 taps of template z as complex128[L] (offsets -L/2 .. L/2-1)."""
+    n = ctypes.c_int32(0)
+    lib().fdas_template_taps(int(z), None, 0, ctypes.byref(n))
+    buf = np.zeros(2 * n.value, dtype=np.float64)
+    _check(lib().fdas_template_taps(int(z), buf.ctypes.data, n.value, ctypes.byref(n)))
+    return buf[0::2] + 1j * buf[1::2]
+
+
+def thresholds(n_harm=8, p_fa=1e-6):
+    out = np.zeros(n_harm, dtype=np.float64)
+    _check(lib().fdas_thresholds(int(n_harm), float(p_fa), out.ctypes.data))
+    return out
+
+
+# ---- torch conveniences ------------------------------------------------------
+
+def fop_ld(n):
+    """Row stride used by the helpers: n rounded up to a multiple of 64 floats."""
+    return (int(n) + 63) // 64 * 64
+
+
+def alloc_fop(plan, n, device="cuda"):
+    import torch
+    return torch.empty((plan.rows, fop_ld(n)), dtype=torch.float32, device=device)
+
+
+def alloc_cands(plan, device="cuda"):
+    import torch
+    nh, cap = plan.desc.n_harm, plan.desc.cand_capacity
+    cands = torch.empty((nh * cap * 4,), dtype=torch.int32, device=device)
+    counts = torch.zeros((nh,), dtype=torch.int32, device=device)
+    return cands, counts
+
+
+def search(plan, spectrum, fop=None, cands=None, counts=None, stream=None):
+    """Both hot-path steps and the readback: (ordered candidates, counts, fop)."""
+    n = spectrum.shape[0]
+    if fop is None:
+        fop = alloc_fop(plan, n, spectrum.device)
+    if cands is None:
+        cands, counts = alloc_cands(plan, spectrum.device)
+    convolve(plan, spectrum, fop, n=n, stream=stream)
+    harmonic_sum(plan, fop, n, cands, counts, stream=stream)
+    c, hc = candidates(plan, cands, counts, stream=stream, allow_overflow=True)
+    return c, hc, fop

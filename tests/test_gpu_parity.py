@@ -1,0 +1,326 @@
+"""GPU parity of the HIP hot path against the CPU oracle (through the C ABI).
+
+* fdas_convolve vs the FP64 oracle FOP: |P - P_ref| <= 1e-4 * max(P_ref, 1)
+  (the FP32 tolerance of the power plane; the floor 1 is the noise mean, where
+  a relative bound alone would blow up on near-zero cells).
+* fdas_harmonic_sum fed the oracle's FOP rounded to FP32 vs the oracle's FP32
+  twin of Algorithm 1: candidate indices and powers bit-exact.
+* End to end (GPU conv + GPU harmonic sum) vs the FP64 oracle: identical
+  candidate lists after excluding cells within 1e-4*T_k of the threshold
+  (guard band), powers within 1e-4 * max(P_ref, k).
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import fop as ofop  # noqa: E402
+from oracle import harmonic as oh  # noqa: E402
+from paper_1806_01556_amd import fdas, synth  # noqa: E402
+
+TOL = 1e-4
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+_plans = {}
+
+
+def plan_for(z_max=42, n_harm=8, n_max=1 << 22, cap=65536, top_k=0):
+    key = (z_max, n_harm, n_max, cap, top_k)
+    if key not in _plans:
+        _plans[key] = fdas.plan_create(z_max=z_max, n_harm=n_harm, n_max=n_max, cand_capacity=cap, top_k=top_k)
+    return _plans[key]
+
+
+def gpu_fop(plan, spec, ld=None):
+    n = spec.shape[0]
+    x = torch.from_numpy(np.ascontiguousarray(spec.astype(np.complex64))).to(_dev())
+    ld = ld or fdas.fop_ld(n)
+    out = torch.full((plan.rows, ld), float("nan"), dtype=torch.float32, device=_dev())
+    fdas.convolve(plan, x, out, n=n)
+    torch.cuda.synchronize()
+    return out
+
+
+def gpu_candidates(plan, fop_t, n, ta=None, allow_overflow=False):
+    cands, counts = fdas.alloc_cands(plan, _dev())
+    ta_t = None if ta is None else torch.from_numpy(np.ascontiguousarray(ta, dtype=np.float32)).to(_dev())
+    fdas.harmonic_sum(plan, fop_t, n, cands, counts, ta=ta_t)
+    c, hc = fdas.candidates(plan, cands, counts, allow_overflow=allow_overflow)
+    return c, hc
+
+
+def assert_fop_close(got, ref):
+    err = np.abs(got.astype(np.float64) - ref)
+    bound = TOL * np.maximum(ref, 1.0)
+    bad = err > bound
+    assert not bad.any(), f"{bad.sum()} cells off; worst ratio {np.max(err / bound):.3g}"
+    return float(np.max(err / bound))
+
+
+# --------------------------------------------------------------------------- conv
+
+@pytest.mark.parametrize("n", [1, 3, 64, 1000, 3703, 3704, 4096, 7407, 12345])
+def test_convolve_ragged_lengths(n):
+    plan = plan_for()
+    spec, _ = synth.make_spectrum(n, 100 + n)
+    got = gpu_fop(plan, spec).cpu().numpy()
+    ref = ofop.fop(spec.astype(np.complex128))
+    assert_fop_close(got[:, :n], ref)
+    assert np.all(np.isnan(got[:, n:])), "columns >= n must not be written"
+
+
+@pytest.mark.parametrize("z_max", [0, 1, 5, 17, 64])
+def test_convolve_other_template_counts(z_max):
+    n = 9000
+    plan = plan_for(z_max=z_max, n_max=1 << 16)
+    spec, _ = synth.make_spectrum(n, 7 + z_max, n_random=2, r_range=(500, 8000))
+    got = gpu_fop(plan, spec).cpu().numpy()[:, :n]
+    ref = ofop.fop(spec.astype(np.complex128), z_max=z_max)
+    assert_fop_close(got, ref)
+
+
+def test_convolve_plain_workload_full_plane():
+    plan = plan_for()
+    spec, _ = synth.plain()
+    n = spec.shape[0]
+    got = gpu_fop(plan, spec).cpu().numpy()[:, :n]
+    ref = ofop.fop(spec.astype(np.complex128))
+    worst = assert_fop_close(got, ref)
+    print(f"plain 2^16: worst |err|/bound = {worst:.3g}", flush=True)
+    # the z = 0 template is a unit delta, so row 0 is |X|^2 up to FP32 rounding
+    p0 = np.abs(spec.astype(np.complex128)) ** 2
+    assert np.max(np.abs(got[42] - p0) / np.maximum(p0, 1.0)) < 1e-5
+
+
+def test_convolve_ska_size_sampled():
+    # Full SKA length in the bench's launch configuration; sampled cells,
+    # each from the direct sum of eq. (1), including every chunk-boundary
+    # column class and the ragged tail.
+    plan = plan_for()
+    spec, _ = synth.ska()
+    n = spec.shape[0]
+    got = gpu_fop(plan, spec).cpu().numpy()
+    V = 4096 - 393
+    rng = np.random.default_rng(5)
+    cols = np.concatenate([rng.integers(0, n, 1500), [0, 1, V - 1, V, V + 1, 2 * V - 1, 500 * V, 500 * V - 1,
+                                                       n - 1, n - 2, n - V]])
+    rows = rng.integers(0, 85, cols.size)
+    ref = ofop.fop_points(spec.astype(np.complex128), rows, cols)
+    assert_fop_close(got[rows, cols], ref)
+    # whole columns around a chunk boundary, all 85 rows
+    cc = np.repeat(np.array([1000 * V - 1, 1000 * V]), 85)
+    rr = np.tile(np.arange(85), 2)
+    assert_fop_close(got[rr, cc], ofop.fop_points(spec.astype(np.complex128), rr, cc))
+
+
+def test_convolve_is_deterministic():
+    plan = plan_for()
+    spec, _ = synth.make_spectrum(50000, 77, n_random=3, r_range=(1000, 40000))
+    a = gpu_fop(plan, spec)
+    b = gpu_fop(plan, spec)
+    assert torch.equal(a[:, :50000], b[:, :50000])
+
+
+def test_convolve_argument_errors():
+    plan = plan_for(n_max=1 << 16)
+    x = torch.zeros(1 << 17, dtype=torch.complex64, device=_dev())
+    fop = torch.zeros((85, 1 << 17), dtype=torch.float32, device=_dev())
+    L = fdas.lib()
+    assert L.fdas_convolve(plan.handle, x.data_ptr(), (1 << 16) + 1, fop.data_ptr(), 1 << 17, None) == fdas.ERR_INVALID_ARG
+    assert L.fdas_convolve(plan.handle, x.data_ptr(), 1000, fop.data_ptr(), 999, None) == fdas.ERR_INVALID_ARG
+    assert L.fdas_convolve(plan.handle, x.data_ptr(), 1000, fop.data_ptr(), 1002, None) == fdas.ERR_INVALID_ARG
+    assert L.fdas_convolve(plan.handle, x.data_ptr(), 1000, fop.data_ptr() + 4, 1000, None) == fdas.ERR_INVALID_ARG
+    assert L.fdas_convolve(plan.handle, x.data_ptr(), 0, fop.data_ptr(), 1000, None) == fdas.ERR_INVALID_ARG
+    assert L.fdas_convolve(plan.handle, x.data_ptr() + 4, 1000, fop.data_ptr(), 1000, None) == fdas.ERR_INVALID_ARG
+
+
+# ------------------------------------------------------------------ harmonic sum
+
+def _upload_plane(plane32, ld=None):
+    rows, n = plane32.shape
+    ld = ld or fdas.fop_ld(n)
+    buf = np.zeros((rows, ld), dtype=np.float32)
+    buf[:, :n] = plane32
+    return torch.from_numpy(buf).to(_dev())
+
+
+def _assert_same_cands(got, ref):
+    assert got.size == ref.size, (got.size, ref.size)
+    for f in ("harm", "z", "r"):
+        assert np.array_equal(got[f], ref[f]), f
+    assert np.array_equal(got["power"].astype(np.float32).view(np.int32),
+                          ref["power"].astype(np.float32).view(np.int32))
+
+
+@pytest.mark.parametrize("n_harm", [1, 2, 3, 5, 8])
+def test_harmonic_sum_bit_exact_on_oracle_fop(n_harm):
+    plan = plan_for(n_harm=n_harm)
+    spec, _ = synth.plain()
+    plane = ofop.fop(spec.astype(np.complex128)).astype(np.float32)
+    n = plane.shape[1]
+    # lower thresholds so every plane holds many candidates
+    ta = oh.threshold_array(n_harm, 42, 2e-4).astype(np.float32)
+    got, counts = gpu_candidates(plan, _upload_plane(plane), n, ta=ta)
+    ref = oh.candidates(plane, n_harm, ta=ta)
+    assert np.array_equal(counts, oh.plane_counts(ref, n_harm))
+    _assert_same_cands(got, ref)
+    # default thresholds (p_fa = 1e-6)
+    got, _ = gpu_candidates(plan, _upload_plane(plane), n)
+    _assert_same_cands(got, oh.candidates(plane, n_harm))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 57, 1001, 4099])
+def test_harmonic_sum_ragged_and_tiny(n):
+    plan = plan_for()
+    rng = np.random.default_rng(n)
+    plane = rng.exponential(size=(85, n)).astype(np.float32)
+    ta = oh.threshold_array(8, 42, 0.02).astype(np.float32)
+    got, _ = gpu_candidates(plan, _upload_plane(plane), n, ta=ta)
+    _assert_same_cands(got, oh.candidates(plane, 8, ta=ta))
+
+
+@pytest.mark.parametrize("z_max", [0, 3, 10, 64])
+def test_harmonic_sum_other_row_counts(z_max):
+    rows, n = 2 * z_max + 1, 3000
+    plan = plan_for(z_max=z_max)
+    rng = np.random.default_rng(z_max)
+    plane = rng.exponential(size=(rows, n)).astype(np.float32)
+    ta = oh.threshold_array(8, z_max, 0.01).astype(np.float32)
+    # a row-dependent threshold array exercises TA(k, i)
+    ta = ta * (1.0 + 0.01 * np.arange(rows, dtype=np.float32)[None, :])
+    got, _ = gpu_candidates(plan, _upload_plane(plane), n, ta=ta)
+    _assert_same_cands(got, oh.candidates(plane, 8, ta=ta))
+
+
+WINDOWS_22 = [(0, 1 << 17), ((1 << 21) - (1 << 16), (1 << 21) + (1 << 16)), ((1 << 22) - (1 << 17), 1 << 22)]
+
+
+def _in_windows(c, windows):
+    keep = np.zeros(c.size, dtype=bool)
+    for a, b in windows:
+        keep |= (c["r"] >= a) & (c["r"] < b)
+    return c[keep]
+
+
+def _windowed_ref(plane, windows, **kw):
+    parts = [oh.candidates(plane, cols=np.arange(a, b), **kw) for a, b in windows]
+    allc = np.concatenate(parts)
+    return allc[np.lexsort((allc["r"], allc["z"], allc["harm"]))]
+
+
+def test_harmonic_sum_full_size_bit_exact():
+    # 85 x 2^22 random exponential plane (the bench's size); the oracle's FP32
+    # twin evaluates three column windows (low, middle, top), every row.
+    plan = plan_for()
+    n = 1 << 22
+    rng = np.random.default_rng(2024)
+    plane = rng.exponential(size=(85, n)).astype(np.float32)
+    plane[40:45, 2_000_000:2_000_010] += 30.0
+    plane[30:34, 65_000:65_012] += 20.0
+    got, counts = gpu_candidates(plan, _upload_plane(plane), n)
+    ref = _windowed_ref(plane, WINDOWS_22, n_harm=8)
+    print(f"2^22 harmonic sum: per plane {counts.tolist()}, windowed ref {ref.size}", flush=True)
+    _assert_same_cands(_in_windows(got, WINDOWS_22), ref)
+
+
+def test_harmonic_sum_capacity_overflow_keeps_true_counts():
+    plan = plan_for(cap=16)
+    rng = np.random.default_rng(1)
+    n = 5000
+    plane = (rng.exponential(size=(85, n)) * 5).astype(np.float32)
+    ta = oh.threshold_array(8, 42, 0.01).astype(np.float32)
+    cands, counts = fdas.alloc_cands(plan, _dev())
+    ta_t = torch.from_numpy(ta).to(_dev())
+    fdas.harmonic_sum(plan, _upload_plane(plane), n, cands, counts, ta=ta_t)
+    with pytest.raises(fdas.FdasError) as e:
+        fdas.candidates(plan, cands, counts)
+    assert e.value.status == fdas.ERR_CAPACITY
+    ref = oh.candidates(plane, 8, ta=ta)
+    assert np.array_equal(counts.cpu().numpy(), oh.plane_counts(ref))
+    got, hc = fdas.candidates(plan, cands, counts, allow_overflow=True)
+    assert got.size == 8 * 16
+    refset = set(zip(ref["harm"].tolist(), ref["z"].tolist(), ref["r"].tolist()))
+    assert all(k in refset for k in zip(got["harm"].tolist(), got["z"].tolist(), got["r"].tolist()))
+
+
+def test_top_k_paper_mode():
+    plan = plan_for(top_k=200)
+    rng = np.random.default_rng(8)
+    n = 20000
+    plane = rng.exponential(size=(85, n)).astype(np.float32)
+    ta = oh.threshold_array(8, 42, 0.01).astype(np.float32)
+    got, _ = gpu_candidates(plan, _upload_plane(plane), n, ta=ta)
+    _assert_same_cands(got, oh.candidates(plane, 8, ta=ta, top_k=200))
+
+
+# --------------------------------------------------------------------- end to end
+
+def _compare_end_to_end(got, plane64, n_harm=8):
+    ref = oh.candidates(plane64, n_harm)
+    guard = oh.guard_cells(plane64, n_harm)
+    gk = {(int(a), int(b), int(c)): float(p) for a, b, c, p in zip(got["harm"], got["z"], got["r"], got["power"])}
+    rk = {(int(a), int(b), int(c)): float(p) for a, b, c, p in zip(ref["harm"], ref["z"], ref["r"], ref["power"])}
+    only_gpu = set(gk) - set(rk) - guard
+    only_ref = set(rk) - set(gk) - guard
+    assert not only_gpu and not only_ref, (sorted(only_gpu)[:10], sorted(only_ref)[:10])
+    for key in set(gk) & set(rk):
+        k = key[0]
+        assert abs(gk[key] - rk[key]) <= TOL * max(rk[key], k), key
+    return ref, guard
+
+
+def test_end_to_end_plain_workload_and_injection():
+    plan = plan_for()
+    spec, _ = synth.plain()
+    n = spec.shape[0]
+    fop_t = gpu_fop(plan, spec)
+    got, counts = gpu_candidates(plan, fop_t, n)
+    plane64 = ofop.fop(spec.astype(np.complex128))
+    ref, guard = _compare_end_to_end(got, plane64)
+    print(f"plain: {got.size} candidates, guard cells {len(guard)}", flush=True)
+    # the injected pulsar (r = 20000.3, z = 17.5) is found in the first plane
+    hit = [(int(z), int(r)) for h, z, r in zip(got["harm"], got["z"], got["r"]) if h == 1]
+    assert any(z in (17, 18) and r in (20000, 20001) for z, r in hit)
+    # its second harmonic (r = 40000.6, z = 35) is in the FOP too
+    assert any(abs(z - 35) <= 1 and abs(r - 40001) <= 1 for z, r in hit)
+
+
+def test_end_to_end_is_deterministic():
+    plan = plan_for()
+    spec, _ = synth.plain(seed=11)
+    n = spec.shape[0]
+    a, _ = gpu_candidates(plan, gpu_fop(plan, spec), n)
+    b, _ = gpu_candidates(plan, gpu_fop(plan, spec), n)
+    assert np.array_equal(a, b)
+
+
+def test_end_to_end_ska_size_windows():
+    # SKA-sized spectrum (2^22, 16 pulsars): full FP64 oracle plane, candidate
+    # lists compared in three column windows.
+    plan = plan_for()
+    spec, _ = synth.ska()
+    n = spec.shape[0]
+    got, counts = gpu_candidates(plan, gpu_fop(plan, spec), n)
+    import os
+    plane64 = ofop.fop(spec.astype(np.complex128), workers=min(16, os.cpu_count() or 1))
+    ref_parts, guard = [], set()
+    for a, b in WINDOWS_22:
+        cols = np.arange(a, b)
+        ref_parts.append(oh.candidates(plane64, 8, cols=cols))
+        guard |= oh.guard_cells(plane64, 8, cols=cols)
+    ref = np.concatenate(ref_parts)
+    gw = _in_windows(got, WINDOWS_22)
+    gk = {(int(a), int(b), int(c)): float(p) for a, b, c, p in zip(gw["harm"], gw["z"], gw["r"], gw["power"])}
+    rk = {(int(a), int(b), int(c)): float(p) for a, b, c, p in zip(ref["harm"], ref["z"], ref["r"], ref["power"])}
+    assert not (set(gk) - set(rk) - guard) and not (set(rk) - set(gk) - guard)
+    for key in set(gk) & set(rk):
+        assert abs(gk[key] - rk[key]) <= TOL * max(rk[key], key[0]), key
+    print(f"ska: {counts.tolist()} per plane; windows {len(rk)} ref, guard {len(guard)}", flush=True)

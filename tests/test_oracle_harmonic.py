@@ -158,3 +158,13 @@ def test_fp32_twin_sums_in_k_order():
             cols = harmonic.stretch_cols(k, p.shape[1])
             acc = (acc + p[rows][:, cols]).astype(np.float32)
         assert np.array_equal(hp, acc)
+
+
+def test_column_window_equals_restriction_of_full_plane():
+    rng = np.random.default_rng(1)
+    p = rng.exponential(size=(85, 6000)) * 3
+    full = harmonic.candidates(p, 8)
+    w = np.arange(2000, 3500)
+    win = harmonic.candidates(p, 8, cols=w)
+    sel = full[(full["r"] >= 2000) & (full["r"] < 3500)]
+    assert win.size > 1000 and np.array_equal(sel, win)
