@@ -124,7 +124,7 @@ def main():
         fdas.harmonic_sum(plan, fop, n, cands, counts, stream=stream)
         if ev:
             ev[2].record(stream)
-        c, hc = fdas.candidates(plan, cands, counts, stream=stream, allow_overflow=True)
+        c, hc = fdas.candidates(plan, cands, counts, stream=stream, allow_overflow=True, copy=False)
         return c, hc
 
     for _ in range(args.warmup):

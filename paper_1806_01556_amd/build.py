@@ -39,6 +39,7 @@ def build(verbose=False):
         "-shared",
         f"--offload-arch={ARCH}",
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        "-fno-slp-vectorize",
         "-Wno-unused-command-line-argument",
         "-I", os.path.join(os.path.dirname(HERE), "include"),
         "-pthread",

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -23,6 +24,13 @@ struct fdas_plan {
   float2* d_tw2 = nullptr;  // [16][16]
   float* d_ta = nullptr;    // [n_harm][rows] default thresholds
   std::vector<float> h_ta;
+  fdas_cand* d_sort_a = nullptr;  // [n_harm * cand_capacity] packed candidates
+  fdas_cand* d_sort_b = nullptr;  // radix-sort ping-pong buffer
+  int* d_sort_hist = nullptr;     // [256 * tiles] digit histograms
+  int bits_r = 1;                 // bits of the column index in the sort key
+  std::map<int64_t, std::pair<int*, int>> tile_orders;  // n -> (device tile order, workgroups)
+  int4* d_hitrows = nullptr;      // [ceil(n_max/4)] rows with hits (harmonic sum phase 1)
+  int32_t* d_hitrow_count = nullptr;
 };
 
 namespace {
@@ -73,6 +81,12 @@ void free_plan(fdas_plan* p) {
   if (p->d_tw1) (void)hipFree(p->d_tw1);
   if (p->d_tw2) (void)hipFree(p->d_tw2);
   if (p->d_ta) (void)hipFree(p->d_ta);
+  if (p->d_sort_a) (void)hipFree(p->d_sort_a);
+  if (p->d_sort_b) (void)hipFree(p->d_sort_b);
+  if (p->d_sort_hist) (void)hipFree(p->d_sort_hist);
+  for (auto& kv : p->tile_orders) (void)hipFree(kv.second.first);
+  if (p->d_hitrows) (void)hipFree(p->d_hitrows);
+  if (p->d_hitrow_count) (void)hipFree(p->d_hitrow_count);
   delete p;
 }
 
@@ -155,8 +169,8 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   if (desc->n_max < 1 || desc->n_max > ((int64_t)1 << 30))
     return fail(FDAS_ERR_INVALID_ARG, "n_max = %lld outside [1, 2^30]", (long long)desc->n_max);
   if (desc->n_harm < 1 || desc->n_harm > 8) return fail(FDAS_ERR_INVALID_ARG, "n_harm = %d outside [1, 8]", (int)desc->n_harm);
-  if (desc->cand_capacity < 1 || desc->cand_capacity > (1 << 26))
-    return fail(FDAS_ERR_INVALID_ARG, "cand_capacity = %d outside [1, 2^26]", (int)desc->cand_capacity);
+  if (desc->cand_capacity < 1 || desc->cand_capacity > (1 << 22))
+    return fail(FDAS_ERR_INVALID_ARG, "cand_capacity = %d outside [1, 2^22]", (int)desc->cand_capacity);
   if (!(desc->p_fa > 0.0 && desc->p_fa < 1.0)) return fail(FDAS_ERR_INVALID_ARG, "p_fa must lie in (0, 1)");
   if (desc->top_k < 0) return fail(FDAS_ERR_INVALID_ARG, "top_k < 0");
   if (desc->method != FDAS_CONV_AUTO && desc->method != FDAS_CONV_OLS_FFT && desc->method != FDAS_CONV_DIRECT)
@@ -209,6 +223,21 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
     free_plan(p);
     return hip_fail(e, "uploading plan tables");
   }
+  {
+    const size_t total = (size_t)desc->n_harm * desc->cand_capacity;
+    const size_t tiles = (size_t)fdas::sort_tile_count((int)total);
+    if ((e = hipMalloc(&p->d_sort_a, total * sizeof(fdas_cand))) != hipSuccess ||
+        (e = hipMalloc(&p->d_sort_b, total * sizeof(fdas_cand))) != hipSuccess ||
+        (e = hipMalloc(&p->d_sort_hist, 256 * tiles * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&p->d_hitrows, (size_t)((desc->n_max + 3) / 4) * sizeof(int4))) != hipSuccess ||
+        (e = hipMalloc(&p->d_hitrow_count, sizeof(int32_t))) != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "allocating the candidate sort workspace");
+    }
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < desc->n_max) ++bits;
+    p->bits_r = bits;
+  }
   *out = p;
   return ok();
 }
@@ -248,10 +277,24 @@ fdas_status fdas_harmonic_sum(fdas_plan* p, const float* d_fop, int64_t n, int64
   DeviceGuard dg(p->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
+  // workgroup -> column-tile order of the 85-row kernel, built once per spectrum length
+  auto it = p->tile_orders.find(n);
+  if (it == p->tile_orders.end()) {
+    std::vector<int> order;
+    fdas::harmsum_tile_order(n, order);
+    int* d_order = nullptr;
+    hipError_t e0 = upload(&d_order, order.data(), order.size() * sizeof(int));
+    if (e0 != hipSuccess) {
+      if (d_order) (void)hipFree(d_order);
+      return hip_fail(e0, "uploading the harmonic-sum tile order");
+    }
+    it = p->tile_orders.emplace(n, std::make_pair(d_order, (int)order.size())).first;
+  }
   hipError_t e = fdas::launch_fill_i32(d_counts, p->desc.n_harm, 0, s);
   if (e != hipSuccess) return hip_fail(e, "clearing the candidate counts");
+  fdas::HsWork wk{it->second.first, it->second.second, p->d_hitrows, p->d_hitrow_count};
   e = fdas::launch_harmsum(d_fop, n, ld, p->desc.z_max, p->desc.n_harm, d_ta ? d_ta : p->d_ta, d_cands,
-                           p->desc.cand_capacity, d_counts, s);
+                           p->desc.cand_capacity, d_counts, wk, s);
   if (e != hipSuccess) return hip_fail(e, "launching the harmonic sum");
   return ok();
 }
@@ -260,6 +303,8 @@ fdas_status fdas_candidates(fdas_plan* p, const fdas_cand* d_cands, const int32_
                             int64_t h_capacity, int64_t* h_n, int32_t* h_counts, void* stream) {
   if (!p) return fail(FDAS_ERR_INVALID_ARG, "plan is NULL");
   if (!d_cands || !d_counts) return fail(FDAS_ERR_INVALID_ARG, "device candidate buffers are NULL");
+  if (reinterpret_cast<uintptr_t>(d_cands) % 16 != 0)
+    return fail(FDAS_ERR_INVALID_ARG, "candidate buffer must be 16-byte aligned");
   if (!h_n) return fail(FDAS_ERR_INVALID_ARG, "h_n is NULL");
   if (h_capacity < 0 || (h_capacity > 0 && !h_out)) return fail(FDAS_ERR_INVALID_ARG, "bad host output buffer");
   *h_n = 0;
@@ -268,44 +313,62 @@ fdas_status fdas_candidates(fdas_plan* p, const fdas_cand* d_cands, const int32_
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nh = p->desc.n_harm;
   const int cap = p->desc.cand_capacity;
-  std::vector<int32_t> counts(nh, 0);
-  hipError_t e = hipMemcpyAsync(counts.data(), d_counts, nh * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  int32_t counts[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  hipError_t e = hipMemcpyAsync(counts, d_counts, nh * sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "reading candidate counts");
-  if (h_counts) std::copy(counts.begin(), counts.end(), h_counts);
+  if (h_counts) std::copy(counts, counts + nh, h_counts);
   bool overflow = false;
-  std::vector<fdas_cand> all;
+  fdas::PackPrefix pp{};
+  pp.nh = nh;
+  pp.off[0] = 0;
   for (int k = 0; k < nh; ++k) {
-    const int c = counts[k];
-    if (c < 0) return fail(FDAS_ERR_DEVICE, "negative candidate count");
-    const int take = std::min(c, cap);
-    if (c > cap) overflow = true;
-    std::vector<fdas_cand> v(take);
-    if (take > 0) {
-      e = hipMemcpyAsync(v.data(), d_cands + (size_t)k * cap, take * sizeof(fdas_cand), hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return hip_fail(e, "reading candidates");
-    }
-    if (p->desc.top_k > 0 && (int)v.size() > p->desc.top_k) {
-      std::sort(v.begin(), v.end(), [](const fdas_cand& a, const fdas_cand& b) {
-        if (a.power != b.power) return a.power > b.power;
-        if (a.z != b.z) return a.z < b.z;
-        return a.r < b.r;
-      });
-      v.resize(p->desc.top_k);
-    }
-    all.insert(all.end(), v.begin(), v.end());
+    if (counts[k] < 0) return fail(FDAS_ERR_DEVICE, "negative candidate count");
+    if (counts[k] > cap) overflow = true;
+    pp.off[k + 1] = pp.off[k] + std::min(counts[k], cap);
   }
-  std::sort(all.begin(), all.end(), [](const fdas_cand& a, const fdas_cand& b) {
-    if (a.harm != b.harm) return a.harm < b.harm;
-    if (a.z != b.z) return a.z < b.z;
-    return a.r < b.r;
-  });
-  const int64_t nw = std::min<int64_t>((int64_t)all.size(), h_capacity);
-  if (nw > 0) std::memcpy(h_out, all.data(), (size_t)nw * sizeof(fdas_cand));
+  const int total = pp.off[nh];
+  fdas_cand* sorted = nullptr;
+  e = fdas::launch_sort_candidates(d_cands, cap, pp, p->rows, p->desc.z_max, p->bits_r, p->d_sort_a,
+                                   p->d_sort_b, p->d_sort_hist, &sorted, s);
+  if (e != hipSuccess) return hip_fail(e, "ordering candidates");
+  int64_t nw = 0;
+  if (p->desc.top_k <= 0) {
+    nw = std::min<int64_t>(total, h_capacity);
+    if (nw > 0) e = hipMemcpyAsync(h_out, sorted, (size_t)nw * sizeof(fdas_cand), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading candidates");
+  } else {
+    // paper mode: each plane keeps its top_k powers (ties: lower z, then lower r)
+    std::vector<fdas_cand> all(total);
+    if (total > 0) e = hipMemcpyAsync(all.data(), sorted, (size_t)total * sizeof(fdas_cand), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading candidates");
+    std::vector<fdas_cand> keep;
+    for (int k = 0; k < nh; ++k) {
+      std::vector<fdas_cand> v(all.begin() + pp.off[k], all.begin() + pp.off[k + 1]);
+      if ((int)v.size() > p->desc.top_k) {
+        std::sort(v.begin(), v.end(), [](const fdas_cand& a, const fdas_cand& b) {
+          if (a.power != b.power) return a.power > b.power;
+          if (a.z != b.z) return a.z < b.z;
+          return a.r < b.r;
+        });
+        v.resize(p->desc.top_k);
+        std::sort(v.begin(), v.end(), [](const fdas_cand& a, const fdas_cand& b) {
+          if (a.z != b.z) return a.z < b.z;
+          return a.r < b.r;
+        });
+      }
+      keep.insert(keep.end(), v.begin(), v.end());
+    }
+    nw = std::min<int64_t>((int64_t)keep.size(), h_capacity);
+    if (nw > 0) std::memcpy(h_out, keep.data(), (size_t)nw * sizeof(fdas_cand));
+    if (nw < (int64_t)keep.size()) overflow = true;
+  }
   *h_n = nw;
   if (overflow) return fail(FDAS_ERR_CAPACITY, "a device candidate list overflowed (counts are exact)");
-  if (nw < (int64_t)all.size()) return fail(FDAS_ERR_CAPACITY, "h_capacity %lld < %zu candidates", (long long)h_capacity, all.size());
+  if (p->desc.top_k <= 0 && nw < total)
+    return fail(FDAS_ERR_CAPACITY, "h_capacity %lld < %d candidates", (long long)h_capacity, total);
   return ok();
 }
 

@@ -36,10 +36,41 @@ hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld,
                            const float2* H, const float2* tw1, const float2* tw2,
                            int rows, int tpg, const OlsGeom& g, hipStream_t s);
 
+// Columns handled by one workgroup of the 85-row harmonic-sum kernel.
+int harmsum_tile_columns();
+
+// Order in which the 85-row harmonic-sum kernel visits its column tiles:
+// tile_of_block[b] is the tile of workgroup b (-1: none), `blocks` entries.
+void harmsum_tile_order(int64_t n, std::vector<int>& tile_of_block);
+
+// Workspace of the two-phase 85-row harmonic sum.
+struct HsWork {
+  const int* tile_of_block;  // workgroup -> column tile (-1: none)
+  int blocks;                // workgroups of phase 1
+  int4* hitrows;             // {j0, row mask words}: ceil(n/4) entries at most
+  int32_t* hitrow_count;     // entries appended by phase 1
+};
+
 hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, int n_harm,
                           const float* ta, fdas_cand* cands, int cap, int32_t* counts,
-                          hipStream_t s);
+                          const HsWork& wk, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s);
+
+// Offsets of the per-plane candidate lists inside the packed array:
+// plane k occupies [off[k], off[k+1]); off[nh] is the total.
+struct PackPrefix {
+  int nh;
+  int off[9];
+};
+
+int sort_tile_count(int m);
+
+// Pack the per-plane lists (planes + k*cap, off[k+1]-off[k] records each)
+// into `a` and order them by (harm, z, r).  `b` is scratch of the same size,
+// `hist` holds 256 * sort_tile_count(total) ints.  *sorted receives a or b.
+hipError_t launch_sort_candidates(const fdas_cand* planes, int cap, const PackPrefix& pp, int rows, int z_max,
+                                  int bits_r, fdas_cand* a, fdas_cand* b, int* hist, fdas_cand** sorted,
+                                  hipStream_t s);
 
 }  // namespace fdas

@@ -219,4 +219,38 @@ double erlang_threshold(int k, double p_fa) {
   return t;
 }
 
+// Tile order of the harmonic-sum kernel.  The stretched reads of tile t come
+// from tiles t/k; for k = 2, 4, 8 these are the doubling chain below t.  Tiles
+// are sorted by the fraction of log2(t) (the bits after the leading one,
+// left-aligned) and then by octave, which puts every chain t, 2t(+1), 4t(+3),
+// 8t(+7) next to each other, so a tile's k = 2, 4, 8 sources were read moments
+// before.  The sorted list is split into 8 contiguous segments, one per XCD
+// (workgroup b runs on XCD b mod 8), so a chain also shares one L2.
+void harmsum_tile_order(int64_t n, std::vector<int>& tile_of_block) {
+  const int64_t cols = harmsum_tile_columns();
+  const int T = (int)((n + cols - 1) / cols);
+  int top = 0;
+  while ((1LL << (top + 1)) <= (int64_t)std::max(1, T - 1)) ++top;  // octave of the largest tile index
+  std::vector<std::pair<uint64_t, int>> key(T);
+  for (int t = 0; t < T; ++t) {
+    if (t == 0) {
+      key[t] = {0, t};
+      continue;
+    }
+    int o = 0;
+    while ((1LL << (o + 1)) <= t) ++o;
+    const uint64_t frac = (uint64_t)(t - (1LL << o)) << (top - o);
+    key[t] = {(frac << 6) | (uint64_t)(o + 1), t};
+  }
+  std::sort(key.begin(), key.end());
+  const int xcd = 8;
+  const int per = (T + xcd - 1) / xcd;
+  tile_of_block.assign((size_t)per * xcd, -1);
+  for (int b = 0; b < per * xcd; ++b) {
+    const int seg = b % xcd, q = b / xcd;
+    const int idx = seg * per + q;
+    if (q < per && idx < T) tile_of_block[b] = key[idx].second;
+  }
+}
+
 }  // namespace fdas

@@ -6,14 +6,10 @@
 //   HP_k(i, j) = HP_{k-1}(i, j) + FOP(trunc(i/k), floor(j/k)),  k = 2..NH
 //   a cell with HP_k(i, j) > TA(k, i) is appended to list k.
 //
-// Each thread owns 4 adjacent columns j0..j0+3 (one 16-byte load per row of
-// the unstretched plane) and walks all rows; for k >= 2 the 4 columns read at
-// most two adjacent source columns (floor(j/k) spans <= 2 values when
-// k >= 2), fetched once per change of the source row trunc(i/k) and kept in
-// registers across the k rows that share it.  Sums are FP32 in k order (no
-// reassociation), so results are bit-identical to a sequential FP32 sum.
-// Candidates are appended with one atomic per plane per hit; the compiler's
-// wave-level atomic aggregation combines hits of a wave.
+// Sums are FP32 in k order (no reassociation, no contraction: there are only
+// additions), so every kernel here is bit-identical to a sequential FP32 sum.
+// Each thread owns 4 adjacent columns j0..j0+3; for k >= 2 those columns read
+// at most two adjacent source columns (floor(j/k) spans <= 2 values).
 
 #include "fdas_internal.h"
 
@@ -31,6 +27,9 @@ __device__ __forceinline__ void emit(int k, int i, int j, float p, fdas_cand* __
   }
 }
 
+// ---------------------------------------------------------------------------
+// Generic path (any row count): runtime row loop; a source value of harmonic k
+// is fetched once per change of trunc(i/k) and kept across the k rows sharing it.
 template <int NH>
 __global__ __launch_bounds__(HS_THREADS) void k_harmsum(const float* __restrict__ fop, int64_t ld, int n,
                                                         int z_max, const float* __restrict__ ta,
@@ -98,6 +97,247 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum(const float* __restrict_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fast path for a compile-time row count (2*Z+1 rows), in two phases.
+//
+// Phase 1 (k_harmsum_z): each thread owns 4 adjacent columns and walks all
+// rows.  Rows and harmonics are unrolled at compile time (template
+// recursion), so every source row and register slot is a constant.  Loads are
+// issued DEPTH rows ahead of their use: the unstretched row r+DEPTH, and for
+// each k >= 2 the source row trunc((r+DEPTH-Z)/k) when it first appears.  A
+// row costs 4*(NH-1) adds plus one max-reduction and compare per harmonic; the
+// thread only records which of its rows hold a cell above threshold (a bit
+// mask), and a block appends one entry {j0, mask} per thread with hits to a
+// global list.
+//
+// Phase 2 (k_harmsum_emit): a grid-stride kernel gives every (entry, row) with
+// its bit set to one thread, which re-forms that row's sums from memory in the
+// same k order (bit-identical to phase 1) and appends the candidates.  Hits
+// cluster around strong pulsars, so spreading them over the whole GPU keeps a
+// few dense tiles from serialising the kernel.
+//
+// Source columns of the 4 columns j0..j0+3 (j0 = 4g) for harmonic k:
+//   k = 2:        (j0/2, j0/2, j0/2+1, j0/2+1)        -- fixed pattern
+//   k = 4, 8:     j0/k for all four (j0 mod k + 3 < k)
+//   k = 3,5,6,7:  column a reads j0/k + 1 iff (j0 mod k) + a >= k
+
+constexpr int DEPTH = 8;
+constexpr int RING = DEPTH / 2 + 3;  // > source rows of one harmonic first used within DEPTH rows
+
+__host__ __device__ constexpr int src_row(int r, int m, int Z) { return (r - Z) / m + Z; }  // C truncation
+__host__ __device__ constexpr int slot_of(int r, int m, int Z) { return (src_row(r, m, Z) - src_row(0, m, Z)) % RING; }
+__host__ __device__ constexpr bool starts(int r, int m, int Z) {
+  return r == 0 || src_row(r, m, Z) != src_row(r - 1, m, Z);
+}
+__host__ __device__ constexpr bool needs_hi(int m) { return m != 4 && m != 8; }
+
+template <int NH>
+struct HsState {
+  float4 ring1[DEPTH];
+  float lo_ring[NH + 1][RING];
+  float hi_ring[NH + 1][RING];
+  float val[NH + 1][4];
+  unsigned hitmask[3];
+};
+
+// loads of the stretched source rows first needed at row R
+template <int Z, int NH, int R, int M>
+__device__ __forceinline__ void hs_issue_m(HsState<NH>& st, const float* __restrict__ fop, int64_t ld,
+                                           const int (&lo)[NH + 1]) {
+  if constexpr (M <= NH) {
+    if constexpr (starts(R, M, Z)) {
+      constexpr int S = src_row(R, M, Z);
+      constexpr int SL = slot_of(R, M, Z);
+      const float* src = fop + (size_t)S * ld + lo[M];
+      if constexpr (M == 2) {
+        const float2 q = *reinterpret_cast<const float2*>(src);  // j0/2 is even
+        st.lo_ring[M][SL] = q.x;
+        st.hi_ring[M][SL] = q.y;
+      } else {
+        st.lo_ring[M][SL] = src[0];
+        if constexpr (needs_hi(M)) st.hi_ring[M][SL] = src[1];
+      }
+    }
+    hs_issue_m<Z, NH, R, M + 1>(st, fop, ld, lo);
+  }
+}
+
+template <int Z, int NH, int R>
+__device__ __forceinline__ void hs_issue(HsState<NH>& st, const float* __restrict__ fop, int64_t ld, int j0,
+                                         const int (&lo)[NH + 1]) {
+  if constexpr (R < 2 * Z + 1) {
+    st.ring1[R % DEPTH] = *reinterpret_cast<const float4*>(fop + (size_t)R * ld + j0);
+    hs_issue_m<Z, NH, R, 2>(st, fop, ld, lo);
+  }
+}
+
+template <int Z, int NH, int R, int M>
+__device__ __forceinline__ void hs_harm(HsState<NH>& st, float (&hp)[4], bool& hit, const int (&rmod)[NH + 1],
+                                        const float* __restrict__ s_ta) {
+  if constexpr (M <= NH) {
+    if constexpr (starts(R, M, Z)) {
+      constexpr int SL = slot_of(R, M, Z);
+      const float vl = st.lo_ring[M][SL];
+      if constexpr (M == 2) {
+        const float vh = st.hi_ring[M][SL];
+        st.val[M][0] = vl;
+        st.val[M][1] = vl;
+        st.val[M][2] = vh;
+        st.val[M][3] = vh;
+      } else if constexpr (!needs_hi(M)) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) st.val[M][a] = vl;
+      } else {
+        const float vh = st.hi_ring[M][SL];
+        st.val[M][0] = vl;
+#pragma unroll
+        for (int a = 1; a < 4; ++a) st.val[M][a] = (rmod[M] + a >= M) ? vh : vl;
+      }
+    }
+    const float t = s_ta[R * 8 + (M - 1)];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) hp[a] = hp[a] + st.val[M][a];
+    // one compare per harmonic: any of the 4 columns above threshold (NaN never is)
+    hit = hit || fmaxf(fmaxf(hp[0], hp[1]), fmaxf(hp[2], hp[3])) > t;
+    hs_harm<Z, NH, R, M + 1>(st, hp, hit, rmod, s_ta);
+  }
+}
+
+template <int Z, int NH, int R>
+__device__ __forceinline__ void hs_rows(HsState<NH>& st, const float* __restrict__ fop, int64_t ld, int j0,
+                                        const int (&lo)[NH + 1], const int (&rmod)[NH + 1],
+                                        const float* __restrict__ s_ta) {
+  // take row R out of its ring slot before the slot is refilled with row R + DEPTH
+  const float4 v = st.ring1[R % DEPTH];
+  hs_issue<Z, NH, R + DEPTH>(st, fop, ld, j0, lo);
+  float hp[4] = {v.x, v.y, v.z, v.w};
+  bool hit = fmaxf(fmaxf(hp[0], hp[1]), fmaxf(hp[2], hp[3])) > s_ta[R * 8];
+  hs_harm<Z, NH, R, 2>(st, hp, hit, rmod, s_ta);
+  st.hitmask[R / 32] |= hit ? (1u << (R % 32)) : 0u;
+  // Keep the software pipeline as written: the row's sums are consumed here
+  // (an empty asm that reads and rewrites the hit word), and no instruction
+  // crosses the row boundary.
+  __asm__ volatile("" : "+v"(st.hitmask[R / 32]));
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (R + 1 < 2 * Z + 1) hs_rows<Z, NH, R + 1>(st, fop, ld, j0, lo, rmod, s_ta);
+}
+
+template <int Z, int NH, int R>
+__device__ __forceinline__ void hs_prologue(HsState<NH>& st, const float* __restrict__ fop, int64_t ld, int j0,
+                                            const int (&lo)[NH + 1]) {
+  hs_issue<Z, NH, R>(st, fop, ld, j0, lo);
+  if constexpr (R + 1 < DEPTH) hs_prologue<Z, NH, R + 1>(st, fop, ld, j0, lo);
+}
+
+// Phase 1 over all columns [0, n) in groups of 4 (the last group may be
+// partial).  The 16-byte read of the last group stays inside the row because
+// ld >= n and ld % 4 == 0; a source column j/k + 1 read for k >= 2 is at most
+// (n-1)/2 + 1 <= ld - 1.  Values read beyond column n - 1 only reach columns
+// >= n, which phase 2 never emits.
+template <int Z, int NH>
+__global__ __launch_bounds__(HS_THREADS) void k_harmsum_z(const float* __restrict__ fop, int64_t ld, int n,
+                                                          const int* __restrict__ tile_of_block,
+                                                          const float* __restrict__ ta, int4* __restrict__ hitrows,
+                                                          int32_t* __restrict__ hitrow_count) {
+  constexpr int ROWS = 2 * Z + 1;
+  static_assert(ROWS <= 96, "hit mask holds 96 rows");
+  __shared__ float s_ta[ROWS * 8];  // [row][k-1]
+  __shared__ int4 s_ent[HS_THREADS];
+  __shared__ int s_nent, s_base;
+  for (int e = threadIdx.x; e < ROWS * 8; e += HS_THREADS) {
+    const int r = e / 8, m = e % 8;
+    s_ta[e] = m < NH ? ta[m * ROWS + r] : 0.0f;
+  }
+  if (threadIdx.x == 0) s_nent = 0;
+  __syncthreads();
+  const int groups = (n + 3) / 4;
+  const int tile = tile_of_block[blockIdx.x];  // -1: no tile for this block
+  const int g = tile * HS_THREADS + threadIdx.x;
+  if (tile >= 0 && g < groups) {
+    const int j0 = 4 * g;
+    int lo[NH + 1], rmod[NH + 1];
+#pragma unroll
+    for (int m = 0; m <= NH; ++m) {
+      lo[m] = m >= 2 ? j0 / m : 0;
+      rmod[m] = m >= 2 ? j0 - lo[m] * m : 0;
+    }
+    HsState<NH> st;
+    st.hitmask[0] = st.hitmask[1] = st.hitmask[2] = 0u;
+    hs_prologue<Z, NH, 0>(st, fop, ld, j0, lo);
+    hs_rows<Z, NH, 0>(st, fop, ld, j0, lo, rmod, s_ta);
+    if (st.hitmask[0] | st.hitmask[1] | st.hitmask[2]) {
+      const int pos = atomicAdd(&s_nent, 1);
+      s_ent[pos] = make_int4(j0, (int)st.hitmask[0], (int)st.hitmask[1], (int)st.hitmask[2]);
+    }
+  }
+  __syncthreads();
+  const int cnt = s_nent;
+  if (cnt == 0) return;  // uniform
+  if (threadIdx.x == 0) s_base = atomicAdd(hitrow_count, cnt);
+  __syncthreads();
+  if (threadIdx.x < cnt) hitrows[s_base + threadIdx.x] = s_ent[threadIdx.x];
+}
+
+// Phase 2: work item w = entry * ROWS + row, grid-stride over all items.
+template <int Z, int NH>
+__global__ __launch_bounds__(HS_THREADS) void k_harmsum_emit(const float* __restrict__ fop, int64_t ld, int n,
+                                                             const int4* __restrict__ hitrows,
+                                                             const int32_t* __restrict__ hitrow_count,
+                                                             const float* __restrict__ ta,
+                                                             fdas_cand* __restrict__ cands, int cap,
+                                                             int32_t* __restrict__ counts) {
+  constexpr int ROWS = 2 * Z + 1;
+  const int64_t items = (int64_t)(*hitrow_count) * ROWS;
+  for (int64_t w = (int64_t)blockIdx.x * HS_THREADS + threadIdx.x; w < items;
+       w += (int64_t)gridDim.x * HS_THREADS) {
+    const int4 ent = hitrows[w / ROWS];
+    const int r = (int)(w % ROWS);
+    const unsigned word = (unsigned)(r < 32 ? ent.y : (r < 64 ? ent.z : ent.w));
+    if (!((word >> (r % 32)) & 1u)) continue;
+    const int j0 = ent.x;
+    const int i = r - Z;
+    // all loads first (independent), then the sums in k order; every column
+    // index read stays < ld (same bound as phase 1)
+    const float4 v = *reinterpret_cast<const float4*>(fop + (size_t)r * ld + j0);
+    float src[NH + 1][4];
+#pragma unroll
+    for (int m = 2; m <= NH; ++m) {
+      const float* rowp = fop + (size_t)(i / m + Z) * ld;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) src[m][a] = rowp[(j0 + a) / m];
+    }
+    float hk[NH + 1][4];
+    hk[1][0] = v.x;
+    hk[1][1] = v.y;
+    hk[1][2] = v.z;
+    hk[1][3] = v.w;
+#pragma unroll
+    for (int m = 2; m <= NH; ++m)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) hk[m][a] = hk[m - 1][a] + src[m][a];
+    // reserve per plane, then write
+#pragma unroll
+    for (int m = 1; m <= NH; ++m) {
+      const float t = ta[(m - 1) * ROWS + r];
+      int c = 0;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) c += (j0 + a < n && hk[m][a] > t) ? 1 : 0;
+      if (c) {
+        int slot = atomicAdd(&counts[m - 1], c);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (j0 + a < n && hk[m][a] > t) {
+            if (slot < cap)
+              *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
+                  make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
+            ++slot;
+          }
+        }
+      }
+    }
+  }
+}
+
 __global__ void k_fill_i32(int32_t* p, int count, int32_t value) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) p[i] = value;
@@ -105,11 +345,47 @@ __global__ void k_fill_i32(int32_t* p, int count, int32_t value) {
 
 }  // namespace
 
+int harmsum_tile_columns() { return 4 * HS_THREADS; }
+
+hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, dim3((count + 255) / 256), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
 hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, int n_harm, const float* ta,
-                          fdas_cand* cands, int cap, int32_t* counts, hipStream_t s) {
+                          fdas_cand* cands, int cap, int32_t* counts, const HsWork& wk, hipStream_t s) {
+  const int nn = (int)n;
+  if (z_max == 42) {
+    // two-phase fast path for the 85-template plane
+    hipError_t e = launch_fill_i32(wk.hitrow_count, 1, 0, s);
+    if (e != hipSuccess) return e;
+    const unsigned blocks = (unsigned)wk.blocks;
+    const unsigned eblocks = 1024;
+    switch (n_harm) {
+#define FDAS_HSZ_CASE(NH)                                                                                          \
+  case NH:                                                                                                         \
+    hipLaunchKernelGGL((k_harmsum_z<42, NH>), dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, nn, wk.tile_of_block, \
+                       ta, wk.hitrows, wk.hitrow_count);                                                           \
+    hipLaunchKernelGGL((k_harmsum_emit<42, NH>), dim3(eblocks), dim3(HS_THREADS), 0, s, fop, ld, nn, wk.hitrows,   \
+                       wk.hitrow_count, ta, cands, cap, counts);                                                   \
+    break;
+      FDAS_HSZ_CASE(1)
+      FDAS_HSZ_CASE(2)
+      FDAS_HSZ_CASE(3)
+      FDAS_HSZ_CASE(4)
+      FDAS_HSZ_CASE(5)
+      FDAS_HSZ_CASE(6)
+      FDAS_HSZ_CASE(7)
+      FDAS_HSZ_CASE(8)
+#undef FDAS_HSZ_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const int64_t groups = (n + 3) / 4;
   const unsigned blocks = (unsigned)((groups + HS_THREADS - 1) / HS_THREADS);
-  const int nn = (int)n;
   switch (n_harm) {
 #define FDAS_HS_CASE(NH)                                                                                 \
   case NH:                                                                                               \
@@ -128,12 +404,6 @@ hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, in
     default:
       return hipErrorInvalidValue;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s) {
-  if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_fill_i32, dim3((count + 255) / 256), dim3(256), 0, s, p, count, value);
   return hipGetLastError();
 }
 

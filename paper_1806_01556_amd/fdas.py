@@ -152,6 +152,7 @@ class Plan:
         self.handle = handle
         self.desc = desc
         self.rows = 2 * desc.z_max + 1
+        self._host_out = None  # pinned candidate buffer, allocated on first use
 
     def destroy(self):
         if self.handle:
@@ -194,20 +195,39 @@ def harmonic_sum(plan, fop, n, cands, counts, ta=None, ld=None, stream=None):
                                    _ptr(counts), _stream(stream)))
 
 
-def candidates(plan, cands, counts, capacity=None, stream=None, allow_overflow=False):
-    """Ordered candidate records (numpy CAND_DTYPE) and the per-plane device counts."""
+def _pinned_out(plan, capacity):
+    """Reusable page-locked host buffer of `capacity` records (numpy view)."""
+    buf = plan._host_out
+    if buf is None or buf[1].shape[0] < capacity:
+        try:
+            import torch
+            t = torch.empty((capacity * CAND_DTYPE.itemsize,), dtype=torch.uint8, pin_memory=True)
+            arr = t.numpy().view(CAND_DTYPE)
+        except Exception:
+            t, arr = None, np.empty(capacity, dtype=CAND_DTYPE)
+        plan._host_out = buf = (t, arr)
+    return buf[1]
+
+
+def candidates(plan, cands, counts, capacity=None, stream=None, allow_overflow=False, copy=True):
+    """Ordered candidate records (numpy CAND_DTYPE) and the per-plane device counts.
+
+    The library orders the lists on the device and copies them into a
+    page-locked buffer owned by the plan.  With copy=False the returned array
+    is a view of that buffer, overwritten by the plan's next call.
+    """
     nh = plan.desc.n_harm
     if capacity is None:
         capacity = nh * plan.desc.cand_capacity
-    out = np.zeros(capacity, dtype=CAND_DTYPE)
+    out = _pinned_out(plan, capacity)
     hc = np.zeros(nh, dtype=np.int32)
     nw = ctypes.c_int64(0)
     st = lib().fdas_candidates(plan.handle, _ptr(cands), _ptr(counts), out.ctypes.data, int(capacity),
                                ctypes.byref(nw), hc.ctypes.data, _stream(stream))
-    if st == ERR_CAPACITY and allow_overflow:
-        return out[: nw.value], hc
-    _check(st)
-    return out[: nw.value], hc
+    if not (st == ERR_CAPACITY and allow_overflow):
+        _check(st)
+    res = out[: nw.value]
+    return (res.copy() if copy else res), hc
 
 
 def template_taps(z):

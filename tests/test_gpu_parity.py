@@ -251,6 +251,21 @@ def test_harmonic_sum_capacity_overflow_keeps_true_counts():
     assert all(k in refset for k in zip(got["harm"].tolist(), got["z"].tolist(), got["r"].tolist()))
 
 
+def test_candidate_order_large_lists():
+    # ~0.5 M candidates over 8 planes: the device radix sort must return
+    # exactly the oracle's (k, i, j)-ordered list.
+    plan = plan_for(cap=1 << 18)
+    rng = np.random.default_rng(31)
+    n = 1 << 18
+    plane = rng.exponential(size=(85, n)).astype(np.float32)
+    ta = oh.threshold_array(8, 42, 0.003).astype(np.float32)
+    got, counts = gpu_candidates(plan, _upload_plane(plane), n, ta=ta)
+    ref = oh.candidates(plane, 8, ta=ta)
+    print(f"large lists: {ref.size} candidates", flush=True)
+    assert ref.size > 400_000
+    _assert_same_cands(got, ref)
+
+
 def test_top_k_paper_mode():
     plan = plan_for(top_k=200)
     rng = np.random.default_rng(8)
