@@ -18,7 +18,7 @@ struct fdas_plan {
   int rows = 0;          // 2*z_max + 1
   int L_max = 0;         // taps of the longest template
   fdas::OlsGeom geom{};  // overlap-save chunk geometry
-  int tpg = 0;           // templates per workgroup (overlap-save)
+  int conv_slots = 512;  // resident convolution workgroups (2 per compute unit)
   float2* d_H = nullptr;    // [rows][C] template spectra
   float2* d_tw1 = nullptr;  // [16][256]
   float2* d_tw2 = nullptr;  // [16][16]
@@ -197,12 +197,16 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   p->geom.C = fdas::kOlsC;
   p->geom.P = p->L_max / 2;
   p->geom.V = p->geom.C - (p->L_max - 1);
-  p->tpg = 17;
 
   DeviceGuard dg(p->device);
   if (dg.err != hipSuccess) {
     free_plan(p);
     return hip_fail(dg.err, "hipSetDevice");
+  }
+  {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
+      p->conv_slots = 2 * cus;
   }
 
   std::vector<std::vector<std::complex<double>>> bank;
@@ -260,7 +264,7 @@ fdas_status fdas_convolve(fdas_plan* p, const void* d_spectrum, int64_t n, float
   DeviceGuard dg(p->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   hipError_t e = fdas::launch_ols_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1,
-                                       p->d_tw2, p->rows, p->tpg, p->geom, static_cast<hipStream_t>(stream));
+                                       p->d_tw2, p->rows, p->geom, p->conv_slots, static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(e, "launching the overlap-save convolution");
   return ok();
 }

@@ -32,9 +32,10 @@ struct OlsGeom {
 };
 
 // ---- kernel launchers (k_*.hip) -------------------------------------------
+// slots: workgroups resident at once (2 per compute unit).
 hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld,
                            const float2* H, const float2* tw1, const float2* tw2,
-                           int rows, int tpg, const OlsGeom& g, hipStream_t s);
+                           int rows, const OlsGeom& g, int slots, hipStream_t s);
 
 // Columns handled by one workgroup of the 85-row harmonic-sum kernel.
 int harmsum_tile_columns();

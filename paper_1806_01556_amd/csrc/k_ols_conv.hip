@@ -23,6 +23,8 @@
 // LDS access of a half-wave hit distinct banks.  No packed-FP32 instructions
 // are written here (the build disables them).
 
+#include <algorithm>
+
 #include "fdas_internal.h"
 
 namespace fdas {
@@ -151,18 +153,46 @@ __device__ __forceinline__ void fft4096(float2 (&v)[16], const float2 (&tw1)[15]
   for (int r = 0; r < 16; ++r) v[r] = t[r];
 }
 
+// Buffer resource (gfx9 layout, raw access) over `bytes` bytes at `base`.
+// Stores at byte offsets >= bytes are dropped by the hardware range check.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// One template: v = F * H_z, inverse FFT, |y|^2 of the valid outputs.
+// hc holds H_z (this thread's 16 bins); hn receives H_{z+1} when next_ok.
+__device__ __forceinline__ void ols_template(const float2 (&F)[16], const float2 (&hc)[16], float2 (&hn)[16],
+                                             bool next_ok, const float2* __restrict__ Hnext,
+                                             float* __restrict__ out_row, uint32_t out_bytes,
+                                             const float2 (&tw1)[15], const float2 (&tw2)[15],
+                                             float2* __restrict__ buf1, float2* __restrict__ buf2, int tid) {
+  float2 v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) v[r] = cmul(F[r], hc[r]);
+  if (next_ok) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) hn[r] = Hnext[tid + 256 * r];
+  }
+  fft4096<1>(v, tw1, tw2, buf1, buf2, tid);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(out_row, out_bytes);
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    // the b32 store takes raw bits: pass the float's bit pattern, not a converted value
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[r].x * v[r].x + v[r].y * v[r].y), rs,
+                                          (int)((tid + 256 * r) * 4), 0, 0);
+}
+
+// Persistent grid: work item = (chunk, template group), item = chunk * groups + group,
+// visited with stride gridDim.x.
 __global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x, int64_t n,
                                                     float* __restrict__ fop, int64_t ld,
                                                     const float2* __restrict__ H,
                                                     const float2* __restrict__ tw1tab,
                                                     const float2* __restrict__ tw2tab, int rows,
-                                                    int tpg, int V, int P) {
+                                                    int tpg, int groups, int64_t items, int V, int P) {
   __shared__ float2 buf1[16 * RS];
   __shared__ float2 buf2[16 * RS];
   const int tid = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * V;
-  const int z_lo = blockIdx.y * tpg;
-  const int z_hi = min(rows, z_lo + tpg);
 
   float2 tw1[15], tw2[15];
 #pragma unroll
@@ -171,42 +201,42 @@ __global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x
     tw2[k - 1] = tw2tab[k * 16 + (tid & 15)];
   }
 
-  float2 v[16];
-  const int64_t in0 = base - P + tid;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int64_t idx = in0 + 256 * r;
-    v[r] = (idx >= 0 && idx < n) ? x[idx] : make_float2(0.0f, 0.0f);
-  }
-  fft4096<-1>(v, tw1, tw2, buf1, buf2, tid);
-  float2 F[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) F[r] = v[r];
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const int64_t chunk = item / groups;
+    const int grp = (int)(item - chunk * groups);
+    const int64_t base = chunk * V;
+    const int z_lo = grp * tpg;
+    const int z_hi = min(rows, z_lo + tpg);
 
-  // outputs of this chunk that exist: s < V and base + s < n
-  const int64_t lim64 = n - base < (int64_t)V ? n - base : (int64_t)V;
-  const int lim = (int)lim64;
-
-  float2 hn[16];
-  {
-    const float2* Hz = H + (size_t)z_lo * kOlsC + tid;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) hn[r] = Hz[256 * r];
-  }
-  for (int z = z_lo; z < z_hi; ++z) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = cmul(F[r], hn[r]);
-    if (z + 1 < z_hi) {
-      const float2* Hz = H + (size_t)(z + 1) * kOlsC + tid;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) hn[r] = Hz[256 * r];
-    }
-    fft4096<1>(v, tw1, tw2, buf1, buf2, tid);
-    float* out = fop + (size_t)z * ld + base;
+    float2 v[16];
+    const int64_t in0 = base - P + tid;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const int s = tid + 256 * r;
-      if (s < lim) out[s] = v[r].x * v[r].x + v[r].y * v[r].y;
+      const int64_t idx = in0 + 256 * r;
+      v[r] = (idx >= 0 && idx < n) ? x[idx] : make_float2(0.0f, 0.0f);
+    }
+    fft4096<-1>(v, tw1, tw2, buf1, buf2, tid);
+    float2 F[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) F[r] = v[r];
+
+    // valid outputs of this chunk: s < V and base + s < n
+    const int64_t lim64 = n - base < (int64_t)V ? n - base : (int64_t)V;
+    const uint32_t out_bytes = (uint32_t)lim64 * 4u;
+
+    float2 hA[16], hB[16];
+    {
+      const float2* Hz = H + (size_t)z_lo * kOlsC;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) hA[r] = Hz[tid + 256 * r];
+    }
+    // two templates per trip with ping-pong prefetch buffers (no register copies)
+    for (int z = z_lo; z < z_hi; z += 2) {
+      ols_template(F, hA, hB, z + 1 < z_hi, H + (size_t)(z + 1) * kOlsC, fop + (size_t)z * ld + base, out_bytes,
+                   tw1, tw2, buf1, buf2, tid);
+      if (z + 1 < z_hi)
+        ols_template(F, hB, hA, z + 2 < z_hi, H + (size_t)(z + 2) * kOlsC, fop + (size_t)(z + 1) * ld + base,
+                     out_bytes, tw1, tw2, buf1, buf2, tid);
     }
   }
 }
@@ -214,12 +244,30 @@ __global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x
 }  // namespace
 
 hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
-                           const float2* tw1, const float2* tw2, int rows, int tpg, const OlsGeom& g,
+                           const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
                            hipStream_t s) {
   const int64_t chunks = (n + g.V - 1) / g.V;
+  // Choose the template-group size: every work item pays one forward FFT plus
+  // tpg inverse FFTs, and items run in rounds of `slots` resident workgroups.
+  int best_tpg = rows;
+  double best = 1e300;
+  for (int G = 1; G <= rows; ++G) {
+    const int tpg = (rows + G - 1) / G;
+    const int groups = (rows + tpg - 1) / tpg;
+    const int64_t items = chunks * groups;
+    const int64_t rounds = (items + slots - 1) / slots;
+    const double cost = (double)rounds * (tpg + 1);
+    if (cost < best - 1e-9) {
+      best = cost;
+      best_tpg = tpg;
+    }
+  }
+  const int tpg = best_tpg;
   const int groups = (rows + tpg - 1) / tpg;
-  dim3 grid((unsigned)chunks, (unsigned)groups);
-  hipLaunchKernelGGL(k_ols_conv, grid, dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, tpg, g.V, g.P);
+  const int64_t items = chunks * groups;
+  const unsigned grid = (unsigned)std::min<int64_t>(items, slots);
+  hipLaunchKernelGGL(k_ols_conv, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, tpg, groups, items,
+                     g.V, g.P);
   return hipGetLastError();
 }
 
