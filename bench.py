@@ -90,6 +90,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="after timing, copy the FOP buffer 3 times (a plain copy of known size, "
+                         "so HBM counters can be scaled to bytes)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -195,6 +198,14 @@ def main():
         "candidates": ncand,
         "candidates_per_plane": [int(v) for v in hc],
     }
+    if args.calibrate_copy:
+        src = fop.view(-1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calibration_copy_bytes"] = {"read": src.numel() * 4, "write": src.numel() * 4}
+        del dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, n)
     plan.destroy()
