@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "FDAS spectra/s (2^22 pts, 85 templates, 8 harmonics) + % HBM/MFMA roofline"
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 FP32_VECTOR_PEAK_TF = 157.3  # MI355X FP32 vector, published
+FP32_MATRIX_PEAK_TF = 157.3  # MI355X FP32 matrix (dense), published
 
 
 def kernel_source_digest(name):
@@ -90,6 +91,9 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--method", choices=("ols", "direct"), default="ols",
+                    help="FT-convolution method: overlap-save FFT (default, the faster) or the direct "
+                         "correlation on the matrix cores")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy the FOP buffer 3 times (a plain copy of known size, "
                          "so HBM counters can be scaled to bytes)")
@@ -113,7 +117,8 @@ def main():
     n = 1 << 22
     spec, pulsars = synth.ska(n=n, seed=2)
     x = torch.from_numpy(spec).to(dev)
-    plan = fdas.plan_create(n_max=n)
+    method = fdas.CONV_OLS_FFT if args.method == "ols" else fdas.CONV_DIRECT
+    plan = fdas.plan_create(n_max=n, method=method)
     fop = fdas.alloc_fop(plan, n, dev)
     cands, counts = fdas.alloc_cands(plan, dev)
     stream = torch.cuda.current_stream()
@@ -150,12 +155,19 @@ def main():
     readback_ms = max(0.0, ms_per_step - conv_ms - hs_ms)
 
     V = 4096 - 393                                    # valid outputs per 4096-point chunk
-    conv_flop = 85 * 5 * 4096 * 12 / V * n          # algorithmic FFT flops of one launch
     hs_bytes = 4 * 85 * n                            # FOP read once
     conv_bytes = 8 * n + 4 * 85 * n                  # spectrum read + FOP write
+    if args.method == "ols":
+        conv_flop = 85 * 5 * 4096 * 12 / V * n      # algorithmic FFT flops of one launch
+        conv = {"name": "k_ols_conv", "bound": "alu", "peak": FP32_VECTOR_PEAK_TF, "file": "k_ols_conv.hip"}
+    else:
+        taps = sum(2 * (8 + (9 * abs(z) + 1) // 2) for z in range(-42, 43))
+        conv_flop = 8 * taps * n                     # one complex multiply-add per template tap and bin
+        conv = {"name": "k_direct_conv", "bound": "mfma", "peak": FP32_MATRIX_PEAK_TF,
+                "file": "k_direct_conv.hip"}
     kernels = {
-        "k_ols_conv": {"ms": conv_ms, "bound": "alu", "achieved": conv_flop / (conv_ms * 1e-3) / 1e12,
-                       "peak": FP32_VECTOR_PEAK_TF, "unit": "TFLOP/s", "file": "k_ols_conv.hip",
+        conv["name"]: {"ms": conv_ms, "bound": conv["bound"], "achieved": conv_flop / (conv_ms * 1e-3) / 1e12,
+                       "peak": conv["peak"], "unit": "TFLOP/s", "file": conv["file"],
                        "hbm_gbs": conv_bytes / (conv_ms * 1e-3) / 1e9},
         "k_harmsum": {"ms": hs_ms, "bound": "hbm", "achieved": hs_bytes / (hs_ms * 1e-3) / 1e9,
                       "peak": HBM_PEAK_GBS, "unit": "GB/s", "file": "k_harmsum.hip"},
@@ -187,13 +199,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ska_single_spectrum_2^22", "n": n, "templates": 85, "z_max": 42,
                    "harmonics": 8, "p_fa": 1e-6, "pulsars": len(pulsars), "seed": 2,
-                   "method": "ols_fft_c4096"},
+                   "method": "ols_fft_c4096" if args.method == "ols" else "direct_mfma_fp32"},
         "roofline": roof,
         "stages_ms": {"convolve": round(conv_ms, 4), "harmonic_sum": round(hs_ms, 4),
                       "candidates_readback": round(readback_ms, 4)},
         "kernels": {k: {"avg_ms": round(v["ms"], 4), "achieved": round(v["achieved"], 3), "unit": v["unit"],
                         "frac": round(v["achieved"] / v["peak"], 4)} for k, v in kernels.items()},
-        "conv_hbm_gbs": round(kernels["k_ols_conv"]["hbm_gbs"], 1),
+        "conv_hbm_gbs": round(kernels[conv["name"]]["hbm_gbs"], 1),
         "device_spectra_per_s": round(1e3 / (conv_ms + hs_ms), 2),
         "candidates": ncand,
         "candidates_per_plane": [int(v) for v in hc],

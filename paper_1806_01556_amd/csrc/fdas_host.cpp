@@ -19,6 +19,11 @@ struct fdas_plan {
   int L_max = 0;         // taps of the longest template
   fdas::OlsGeom geom{};  // overlap-save chunk geometry
   int conv_slots = 512;  // resident convolution workgroups (2 per compute unit)
+  bool direct = false;      // FDAS_CONV_DIRECT: matrix-core correlation instead of overlap-save
+  float* d_Bpk = nullptr;   // direct: packed template operand
+  int4* d_dtiles = nullptr; // direct: per-tile {P, first pair, members, 0}
+  int* d_drows = nullptr;   // direct: [tiles][8] FOP rows
+  int dtiles = 0, dP_max = 0, dP8_max = 0;
   float2* d_H = nullptr;    // [rows][C] template spectra
   float2* d_tw1 = nullptr;  // [16][256]
   float2* d_tw2 = nullptr;  // [16][16]
@@ -77,6 +82,9 @@ struct DeviceGuard {
 
 void free_plan(fdas_plan* p) {
   if (!p) return;
+  if (p->d_Bpk) (void)hipFree(p->d_Bpk);
+  if (p->d_dtiles) (void)hipFree(p->d_dtiles);
+  if (p->d_drows) (void)hipFree(p->d_drows);
   if (p->d_H) (void)hipFree(p->d_H);
   if (p->d_tw1) (void)hipFree(p->d_tw1);
   if (p->d_tw2) (void)hipFree(p->d_tw2);
@@ -175,8 +183,6 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   if (desc->top_k < 0) return fail(FDAS_ERR_INVALID_ARG, "top_k < 0");
   if (desc->method != FDAS_CONV_AUTO && desc->method != FDAS_CONV_OLS_FFT && desc->method != FDAS_CONV_DIRECT)
     return fail(FDAS_ERR_INVALID_ARG, "unknown method %d", (int)desc->method);
-  if (desc->method == FDAS_CONV_DIRECT)
-    return fail(FDAS_ERR_UNSUPPORTED, "the direct method is not built in this library");
   if (desc->precision != FDAS_PREC_FP32) return fail(FDAS_ERR_UNSUPPORTED, "precision %d is not built", (int)desc->precision);
   if (desc->hsum_index != FDAS_HSUM_STRETCH) return fail(FDAS_ERR_UNSUPPORTED, "hsum_index %d is not built", (int)desc->hsum_index);
   if (desc->ols_chunk != 0 && desc->ols_chunk != fdas::kOlsC)
@@ -211,19 +217,36 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
 
   std::vector<std::vector<std::complex<double>>> bank;
   fdas::template_bank(desc->z_max, bank);
-  std::vector<float> H, tw1, tw2;
-  fdas::ols_spectra(bank, p->geom.C, p->geom.P, H);
-  fdas::fft_twiddles(tw1, tw2);
+  p->direct = desc->method == FDAS_CONV_DIRECT;
+  std::vector<float> H, tw1, tw2, Bpk;
+  std::vector<int> dtiles, drows;
+  if (p->direct) {
+    fdas::direct_pack(bank, desc->z_max, Bpk, dtiles, drows, &p->dP_max, &p->dP8_max);
+    p->dtiles = (int)dtiles.size() / 4;
+  } else {
+    fdas::ols_spectra(bank, p->geom.C, p->geom.P, H);
+    fdas::fft_twiddles(tw1, tw2);
+  }
   p->h_ta.resize((size_t)desc->n_harm * p->rows);
   for (int k = 1; k <= desc->n_harm; ++k) {
     const float t = (float)fdas::erlang_threshold(k, desc->p_fa);
     for (int r = 0; r < p->rows; ++r) p->h_ta[(size_t)(k - 1) * p->rows + r] = t;
   }
 
-  if ((e = upload(&p->d_H, H.data(), H.size() * sizeof(float))) != hipSuccess ||
-      (e = upload(&p->d_tw1, tw1.data(), tw1.size() * sizeof(float))) != hipSuccess ||
-      (e = upload(&p->d_tw2, tw2.data(), tw2.size() * sizeof(float))) != hipSuccess ||
-      (e = upload(&p->d_ta, p->h_ta.data(), p->h_ta.size() * sizeof(float))) != hipSuccess) {
+  if (p->direct) {
+    if ((e = upload(&p->d_Bpk, Bpk.data(), Bpk.size() * sizeof(float))) != hipSuccess ||
+        (e = upload(&p->d_dtiles, dtiles.data(), dtiles.size() * sizeof(int))) != hipSuccess ||
+        (e = upload(&p->d_drows, drows.data(), drows.size() * sizeof(int))) != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "uploading the direct-method template operand");
+    }
+  } else if ((e = upload(&p->d_H, H.data(), H.size() * sizeof(float))) != hipSuccess ||
+             (e = upload(&p->d_tw1, tw1.data(), tw1.size() * sizeof(float))) != hipSuccess ||
+             (e = upload(&p->d_tw2, tw2.data(), tw2.size() * sizeof(float))) != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "uploading the overlap-save template spectra");
+  }
+  if ((e = upload(&p->d_ta, p->h_ta.data(), p->h_ta.size() * sizeof(float))) != hipSuccess) {
     free_plan(p);
     return hip_fail(e, "uploading plan tables");
   }
@@ -263,9 +286,17 @@ fdas_status fdas_convolve(fdas_plan* p, const void* d_spectrum, int64_t n, float
   if (st != FDAS_OK) return st;
   DeviceGuard dg(p->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
-  hipError_t e = fdas::launch_ols_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1,
-                                       p->d_tw2, p->rows, p->geom, p->conv_slots, static_cast<hipStream_t>(stream));
-  if (e != hipSuccess) return hip_fail(e, "launching the overlap-save convolution");
+  hipError_t e;
+  if (p->direct) {
+    const fdas::DirectTables t{p->d_Bpk, p->d_dtiles, p->d_drows, p->dtiles, p->dP_max, p->dP8_max};
+    e = fdas::launch_direct_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, t,
+                                 static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "launching the direct correlation");
+  } else {
+    e = fdas::launch_ols_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2,
+                              p->rows, p->geom, p->conv_slots, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "launching the overlap-save convolution");
+  }
   return ok();
 }
 

@@ -21,6 +21,14 @@ void ols_spectra(const std::vector<std::vector<std::complex<double>>>& bank, int
 void fft_twiddles(std::vector<float>& tw1, std::vector<float>& tw2);
 double erlang_threshold(int k, double p_fa);
 
+// Packed template operand of the direct (matrix-core) correlation: templates
+// ordered by |z| (0, -1, 1, -2, 2, ...) in tiles of 8; tile g covers taps
+// [-P_g, P_g - 1] in P_g pairs of 64 lane-ordered floats (zero-padded to a
+// multiple of 8 pairs).  tiles[g] = {P_g, first pair, members, padded pairs};
+// rows[8 g + t] = FOP row of member t.
+void direct_pack(const std::vector<std::vector<std::complex<double>>>& bank, int z_max, std::vector<float>& Bpk,
+                 std::vector<int>& tiles, std::vector<int>& rows, int* P_max, int* P8_max);
+
 // ---- overlap-save geometry -------------------------------------------------
 constexpr int kOlsC = 4096;      // FFT length of one chunk
 constexpr int kOlsThreads = 256; // threads per workgroup (16 points each)
@@ -36,6 +44,20 @@ struct OlsGeom {
 hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld,
                            const float2* H, const float2* tw1, const float2* tw2,
                            int rows, const OlsGeom& g, int slots, hipStream_t s);
+
+struct DirectTables {
+  const float* Bpk;    // packed template operand
+  const int4* tiles;   // per tile {P, first pair, members, padded pairs}
+  const int* rows;     // [ntiles][8] FOP rows
+  int ntiles;
+  int P_max;    // largest P over the tiles
+  int P8_max;   // largest padded pair count
+};
+int direct_block_bins();
+int direct_max_half_taps();
+size_t direct_lds_bytes(int P_max, int P8_max);
+hipError_t launch_direct_conv(const float2* x, int64_t n, float* fop, int64_t ld, const DirectTables& t,
+                              hipStream_t s);
 
 // Columns handled by one workgroup of the 85-row harmonic-sum kernel.
 int harmsum_tile_columns();

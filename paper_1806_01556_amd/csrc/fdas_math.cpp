@@ -169,6 +169,57 @@ void ols_spectra(const std::vector<std::vector<cd>>& bank, int C, int P, std::ve
   for (auto& t : th) t.join();
 }
 
+void direct_pack(const std::vector<std::vector<cd>>& bank, int z_max, std::vector<float>& Bpk,
+                 std::vector<int>& tiles, std::vector<int>& rows, int* P_max, int* P8_max) {
+  // member order by |z|: 0, -1, 1, -2, 2, ...
+  std::vector<int> order;
+  order.push_back(0);
+  for (int a = 1; a <= z_max; ++a) {
+    order.push_back(-a);
+    order.push_back(a);
+  }
+  const int T = ((int)order.size() + 7) / 8;
+  tiles.assign((size_t)T * 4, 0);
+  rows.assign((size_t)T * 8, -1);
+  Bpk.clear();
+  int pairs = 0, pm = 0, p8m = 0;
+  for (int g = 0; g < T; ++g) {
+    const int cnt = std::min(8, (int)order.size() - 8 * g);
+    int P = 0;
+    for (int t = 0; t < cnt; ++t) P = std::max(P, tap_count(order[8 * g + t]) / 2);
+    const int P8 = (P + 7) / 8 * 8;  // pairs padded with zero values to a multiple of 8
+    pm = std::max(pm, P);
+    p8m = std::max(p8m, P8);
+    tiles[4 * g + 0] = P;
+    tiles[4 * g + 1] = pairs;
+    tiles[4 * g + 2] = cnt;
+    tiles[4 * g + 3] = P8;
+    for (int t = 0; t < cnt; ++t) rows[8 * g + t] = order[8 * g + t] + z_max;
+    for (int p = 0; p < P8; ++p) {
+      for (int lane = 0; lane < 64; ++lane) {
+        const int col = lane & 15, k = lane >> 4;
+        const int slot = col >> 1, part = col & 1;
+        const int d = -P + 2 * p + (k >> 1);  // tap of this k
+        cd h(0.0, 0.0);
+        if (slot < cnt && p < P) {
+          const int z = order[8 * g + slot];
+          const std::vector<cd>& hz = bank[z + z_max];
+          const int L = (int)hz.size();
+          const int t = d + L / 2;
+          if (t >= 0 && t < L) h = hz[t];
+        }
+        // (Re X, Im X) against the Re-column: (Re h, -Im h); against the Im-column: (Im h, Re h)
+        const bool im_x = (k & 1) != 0;
+        const double v = part == 0 ? (im_x ? -h.imag() : h.real()) : (im_x ? h.real() : h.imag());
+        Bpk.push_back((float)v);
+      }
+    }
+    pairs += P8;
+  }
+  *P_max = pm;
+  *P8_max = p8m;
+}
+
 void fft_twiddles(std::vector<float>& tw1, std::vector<float>& tw2) {
   // tw1[nb][t] = e^{+2 pi i nb t / 4096} (nb < 16, t < 256); tw2[q][c] = e^{+2 pi i q c / 256}.
   tw1.assign(16 * 256 * 2, 0.0f);

@@ -1,0 +1,158 @@
+// Direct FIR correlation of the spectrum with every acceleration template on
+// the matrix cores, fused with the power (Section 2.1.1, eq. (1): the
+// time-domain FIR form, here as a Toeplitz-window x template contraction).
+//
+//   Y[j, z] = sum_d X[j + d] h_z[d],   FOP[z + z_max][j] = |Y[j, z]|^2.
+//
+// As a matrix product, row j of the window matrix is X[j + d] over the taps d
+// and column z of the template matrix is h_z[d]; the window matrix is never
+// formed: a workgroup stages its strip of X in LDS once and every MFMA operand
+// is read from the strip at offset (row + tap).
+//
+// MFMA mapping (v_mfma_f32_16x16x4f32, one 16 x 16 FP32 output block,
+// K = 4 real values = 2 complex taps per instruction):
+//   rows    = 16 consecutive output bins;
+//   columns = 8 templates x {Re Y, Im Y};
+//   k       = (tap d, Re X), (d, Im X), (d + 1, Re X), (d + 1, Im X).
+// With X = a + ib and h = c + is, Re Y += a c - b s and Im Y += a s + b c, so
+// the packed template operand holds (c, -s) in the Re-column and (s, c) in the
+// Im-column for the (Re X, Im X) pair of each tap; the plan packs it in lane
+// order, 64 floats per tap pair.
+//
+// Templates are grouped by |z| in tiles of 8, and a tile only runs over the
+// union of its members' supports [-P, P-1] (P = largest L/2 in the tile), so
+// short templates do not pay for the 394-tap ones.  After the tap loop the
+// lane holding Re Y and its neighbour holding Im Y swap values (DPP quad
+// permutation), form |Y|^2, and store two bins each.
+//
+// Work split: a workgroup = 4 waves covers 512 consecutive bins; a wave owns
+// 8 sub-tiles of 16 bins (8 independent accumulators keep the MFMA pipe full
+// without waiting on one accumulator chain) and runs every template tile.
+
+#include "fdas_internal.h"
+
+namespace fdas {
+namespace {
+
+constexpr int DW = 4;                 // waves per workgroup
+constexpr int SUB = 8;                // 16-bin sub-tiles per wave
+constexpr int WAVE_BINS = 16 * SUB;   // 128
+constexpr int BLK_BINS = DW * WAVE_BINS;  // 512
+constexpr int MAX_P = 296;            // L(64)/2, the widest template the plan allows
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// value of the neighbouring lane (lanes 2q and 2q+1 swap)
+__device__ __forceinline__ float swap_pair(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+
+// tiles[g] = {P (tap pairs), first tap pair in Bpk, member count, P rounded up to 8};
+// rows[g * 8 + t] = FOP row of member t.  Dynamic LDS: the X strip
+// (2 * (BLK_BINS + 2 Pm + 16) floats) followed by one tile's template operand
+// (64 * max padded pairs floats).
+__global__ __launch_bounds__(DW * 64) void k_direct_conv(const float2* __restrict__ x, int64_t n,
+                                                         float* __restrict__ fop, int64_t ld,
+                                                         const float* __restrict__ Bpk,
+                                                         const int4* __restrict__ tiles,
+                                                         const int* __restrict__ rows, int ntiles, int Pm) {
+  extern __shared__ float4 lds4[];
+  float* xs = reinterpret_cast<float*>(lds4);
+  const int tid = threadIdx.x;
+  const int64_t jb = (int64_t)blockIdx.x * BLK_BINS;
+  // strip X[jb - Pm + u], u < BLK_BINS + 2 Pm, plus 16 bins read (against
+  // zero template values) by the padding pairs of a tile's last group of 8
+  const int strip = BLK_BINS + 2 * Pm + 16;
+  float* bs = xs + 2 * strip;  // strip is a multiple of 8 bins: bs stays 16-byte aligned
+  for (int u = tid; u < strip; u += DW * 64) {
+    const int64_t idx = jb - Pm + u;
+    const float2 v = (idx >= 0 && idx < n) ? x[idx] : make_float2(0.0f, 0.0f);
+    xs[2 * u] = v.x;
+    xs[2 * u + 1] = v.y;
+  }
+
+  const int lane = tid & 63;
+  const int w = tid >> 6;
+  const int m = lane & 15;  // A row (bin) / output column
+  const int kk = lane >> 4; // A/B k index; output row group
+  const int col = lane & 15;
+  const int slot = col >> 1;
+  const int c = col & 1;
+
+  for (int g = 0; g < ntiles; ++g) {
+    const int4 tg = tiles[g];
+    const int P = tg.x;   // tap pairs of the tile's support
+    const int P8 = tg.w;  // P rounded up to 8 (zero-padded in Bpk)
+    {
+      // stage the tile's template operand (P8 * 64 floats) in LDS
+      const float4* __restrict__ src = reinterpret_cast<const float4*>(Bpk + (size_t)tg.y * 64);
+      float4* dst = reinterpret_cast<float4*>(bs);
+      __syncthreads();  // previous tile's operand no longer in use (and the strip is complete)
+      for (int i = tid; i < P8 * 16; i += DW * 64) dst[i] = src[i];
+      __syncthreads();
+    }
+    // this lane's A value of tap pair 0, sub-tile 0; pairs are 4 floats apart, sub-tiles 32
+    const float* __restrict__ a = xs + 2 * (w * WAVE_BINS + m + Pm - P) + kk;
+    const float* __restrict__ b = bs + lane;
+    v4f acc[SUB];
+#pragma unroll
+    for (int s = 0; s < SUB; ++s) acc[s] = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int p = 0; p < P8; p += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const float bv = b[64 * (p + u)];
+#pragma unroll
+        for (int s = 0; s < SUB; ++s)
+          acc[s] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[32 * s + 4 * (p + u)], bv, acc[s], 0, 0, 0);
+      }
+    }
+    const int row = slot < tg.z ? rows[g * 8 + slot] : -1;
+#pragma unroll
+    for (int s = 0; s < SUB; ++s) {
+      float pw[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const float o = swap_pair(acc[s][v]);
+        pw[v] = acc[s][v] * acc[s][v] + o * o;
+      }
+      if (row >= 0) {
+        // this lane stores bins j0 + 2c and j0 + 2c + 1 of its template
+        const int64_t j = jb + w * WAVE_BINS + 16 * s + 4 * kk + 2 * c;
+        float* dst = fop + (size_t)row * ld + j;
+        const float p0 = c ? pw[2] : pw[0];
+        const float p1 = c ? pw[3] : pw[1];
+        if (j + 2 <= n) {
+          *reinterpret_cast<float2*>(dst) = make_float2(p0, p1);
+        } else if (j < n) {
+          dst[0] = p0;
+        }
+      }
+    }
+  }
+}
+
+}  // namespace
+
+int direct_block_bins() { return BLK_BINS; }
+int direct_max_half_taps() { return MAX_P; }
+size_t direct_lds_bytes(int P_max, int P8_max) {
+  return sizeof(float) * (2 * (size_t)(BLK_BINS + 2 * P_max + 16) + 64 * (size_t)P8_max);
+}
+
+hipError_t launch_direct_conv(const float2* x, int64_t n, float* fop, int64_t ld, const DirectTables& t,
+                              hipStream_t s) {
+  if (t.P_max > MAX_P || t.ntiles < 1 || n < 1) return hipErrorInvalidValue;
+  const int64_t blocks = (n + BLK_BINS - 1) / BLK_BINS;
+  const size_t lds = direct_lds_bytes(t.P_max, t.P8_max);
+  if (lds > 65536) {
+    // above 64 KiB (templates wider than |z| = 42) the kernel must opt in
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_direct_conv),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_direct_conv, dim3((unsigned)blocks), dim3(DW * 64), lds, s, x, n, fop, ld, t.Bpk, t.tiles,
+                     t.rows, t.ntiles, t.P_max);
+  return hipGetLastError();
+}
+
+}  // namespace fdas
