@@ -4,7 +4,12 @@ One step = the whole hot path on one SKA-sized spectrum already resident in
 HBM: fdas_convolve (85-template FT convolution + power -> FOP), then
 fdas_harmonic_sum (8 harmonic planes, thresholds, candidate compaction), then
 fdas_candidates (readback + canonical order).  Template generation happens
-once at plan creation and is not timed.
+once at plan creation and is not timed.  Steps are pipelined (--pipeline,
+default 2): step k+1's kernels are queued on a second plan and stream before
+step k's candidates are ordered and copied back, so the host-side readback of
+one spectrum overlaps the GPU work of the next, as in a stream of dispersion
+trials; every step still does all of its work.  The same steps run strictly
+one after the other are reported as serial_ms_per_step.
 
 Prints one JSON line.  Per-kernel durations come from HIP events recorded on
 the stream the library launches on; the roofline object describes the kernel
@@ -94,6 +99,9 @@ def main():
     ap.add_argument("--method", choices=("ols", "direct"), default="ols",
                     help="FT-convolution method: overlap-save FFT (default, the faster) or the direct "
                          "correlation on the matrix cores")
+    ap.add_argument("--pipeline", type=int, default=2,
+                    help="steps in flight: step k+1's kernels are queued before step k's candidates are read "
+                         "back (1 = strictly one step after the other)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy the FOP buffer 3 times (a plain copy of known size, "
                          "so HBM counters can be scaled to bytes)")
@@ -118,41 +126,67 @@ def main():
     spec, pulsars = synth.ska(n=n, seed=2)
     x = torch.from_numpy(spec).to(dev)
     method = fdas.CONV_OLS_FFT if args.method == "ols" else fdas.CONV_DIRECT
-    plan = fdas.plan_create(n_max=n, method=method)
-    fop = fdas.alloc_fop(plan, n, dev)
-    cands, counts = fdas.alloc_cands(plan, dev)
-    stream = torch.cuda.current_stream()
+    P = max(1, args.pipeline)
+    # P independent plans, FOPs, candidate buffers and streams: step k uses
+    # set k % P, so step k's kernels run while step k-1's candidates are
+    # ordered and copied back (a plan is used by one stream at a time)
+    plans = [fdas.plan_create(n_max=n, method=method) for _ in range(P)]
+    fops = [fdas.alloc_fop(plans[i], n, dev) for i in range(P)]
+    bufs = [fdas.alloc_cands(plans[i], dev) for i in range(P)]
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(P - 1)]
 
-    def step(ev=None):
+    def enqueue(k, ev=None):
+        i = k % P
+        st = streams[i]
         if ev:
-            ev[0].record(stream)
-        fdas.convolve(plan, x, fop, n=n, stream=stream)
+            ev[0].record(st)
+        fdas.convolve(plans[i], x, fops[i], n=n, stream=st)
         if ev:
-            ev[1].record(stream)
-        fdas.harmonic_sum(plan, fop, n, cands, counts, stream=stream)
+            ev[1].record(st)
+        fdas.harmonic_sum(plans[i], fops[i], n, bufs[i][0], bufs[i][1], stream=st)
         if ev:
-            ev[2].record(stream)
-        c, hc = fdas.candidates(plan, cands, counts, stream=stream, allow_overflow=True, copy=False)
-        return c, hc
+            ev[2].record(st)
 
-    for _ in range(args.warmup):
-        step()
+    def readback(k):
+        i = k % P
+        return fdas.candidates(plans[i], bufs[i][0], bufs[i][1], stream=streams[i], allow_overflow=True,
+                               copy=False)
+
+    def run(steps, evs=None):
+        out = None
+        for k in range(steps):
+            enqueue(k, evs[k] if evs else None)
+            if k >= P - 1:
+                out = readback(k - P + 1)
+        for k in range(max(0, steps - P + 1), steps):
+            out = readback(k)
+        return out
+
+    run(args.warmup)
     torch.cuda.synchronize()
 
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ncand = 0
-    for k in range(args.steps):
-        c, hc = step(evs[k])
-        ncand = int(c.size)
+    c, hc = run(args.steps, evs)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    ncand = int(c.size)
 
     conv_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
     hs_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     ms_per_step = 1e3 * wall / args.steps
     readback_ms = max(0.0, ms_per_step - conv_ms - hs_ms)
+
+    # the same steps one after another on one stream (no overlap), for reference
+    serial_steps = min(args.steps, 10)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(serial_steps):
+        enqueue(0)
+        readback(0)
+    torch.cuda.synchronize()
+    serial_ms = 1e3 * (time.perf_counter() - t1) / serial_steps
 
     V = 4096 - 393                                    # valid outputs per 4096-point chunk
     hs_bytes = 4 * 85 * n                            # FOP read once
@@ -199,10 +233,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ska_single_spectrum_2^22", "n": n, "templates": 85, "z_max": 42,
                    "harmonics": 8, "p_fa": 1e-6, "pulsars": len(pulsars), "seed": 2,
-                   "method": "ols_fft_c4096" if args.method == "ols" else "direct_mfma_fp32"},
+                   "method": "ols_fft_c4096" if args.method == "ols" else "direct_mfma_fp32",
+                   "pipeline": P},
         "roofline": roof,
         "stages_ms": {"convolve": round(conv_ms, 4), "harmonic_sum": round(hs_ms, 4),
-                      "candidates_readback": round(readback_ms, 4)},
+                      "candidates_readback_not_overlapped": round(readback_ms, 4)},
+        "serial_ms_per_step": round(serial_ms, 4),
         "kernels": {k: {"avg_ms": round(v["ms"], 4), "achieved": round(v["achieved"], 3), "unit": v["unit"],
                         "frac": round(v["achieved"] / v["peak"], 4)} for k, v in kernels.items()},
         "conv_hbm_gbs": round(kernels[conv["name"]]["hbm_gbs"], 1),
@@ -211,7 +247,7 @@ def main():
         "candidates_per_plane": [int(v) for v in hc],
     }
     if args.calibrate_copy:
-        src = fop.view(-1)
+        src = fops[0].view(-1)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
@@ -220,7 +256,8 @@ def main():
         del dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, n)
-    plan.destroy()
+    for pl in plans:
+        pl.destroy()
     print(json.dumps(out), flush=True)
 
 

@@ -32,6 +32,8 @@ struct fdas_plan {
   fdas_cand* d_sort_a = nullptr;  // [n_harm * cand_capacity] packed candidates
   fdas_cand* d_sort_b = nullptr;  // radix-sort ping-pong buffer
   int* d_sort_hist = nullptr;     // [256 * tiles] digit histograms
+  int* d_sort_totals = nullptr;   // [256 * passes] digit totals per pass
+  int32_t* h_counts = nullptr;    // pinned host copy of the device counts
   int bits_r = 1;                 // bits of the column index in the sort key
   std::map<int64_t, std::pair<int*, int>> tile_orders;  // n -> (device tile order, workgroups)
   int4* d_hitrows = nullptr;      // [ceil(n_max/4)] rows with hits (harmonic sum phase 1)
@@ -92,6 +94,8 @@ void free_plan(fdas_plan* p) {
   if (p->d_sort_a) (void)hipFree(p->d_sort_a);
   if (p->d_sort_b) (void)hipFree(p->d_sort_b);
   if (p->d_sort_hist) (void)hipFree(p->d_sort_hist);
+  if (p->d_sort_totals) (void)hipFree(p->d_sort_totals);
+  if (p->h_counts) (void)hipHostFree(p->h_counts);
   for (auto& kv : p->tile_orders) (void)hipFree(kv.second.first);
   if (p->d_hitrows) (void)hipFree(p->d_hitrows);
   if (p->d_hitrow_count) (void)hipFree(p->d_hitrow_count);
@@ -252,17 +256,20 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   }
   {
     const size_t total = (size_t)desc->n_harm * desc->cand_capacity;
+    int bits = 1;
+    while (bits < 31 && ((int64_t)1 << bits) < desc->n_max) ++bits;
     const size_t tiles = (size_t)fdas::sort_tile_count((int)total);
+    const size_t passes = (size_t)fdas::sort_passes(p->rows, bits);
     if ((e = hipMalloc(&p->d_sort_a, total * sizeof(fdas_cand))) != hipSuccess ||
         (e = hipMalloc(&p->d_sort_b, total * sizeof(fdas_cand))) != hipSuccess ||
         (e = hipMalloc(&p->d_sort_hist, 256 * tiles * sizeof(int))) != hipSuccess ||
+        (e = hipMalloc(&p->d_sort_totals, 256 * passes * sizeof(int))) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void**>(&p->h_counts), 8 * sizeof(int32_t), 0)) != hipSuccess ||
         (e = hipMalloc(&p->d_hitrows, (size_t)((desc->n_max + 3) / 4) * sizeof(int4))) != hipSuccess ||
         (e = hipMalloc(&p->d_hitrow_count, sizeof(int32_t))) != hipSuccess) {
       free_plan(p);
       return hip_fail(e, "allocating the candidate sort workspace");
     }
-    int bits = 1;
-    while (bits < 31 && ((int64_t)1 << bits) < desc->n_max) ++bits;
     p->bits_r = bits;
   }
   *out = p;
@@ -348,25 +355,25 @@ fdas_status fdas_candidates(fdas_plan* p, const fdas_cand* d_cands, const int32_
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nh = p->desc.n_harm;
   const int cap = p->desc.cand_capacity;
-  int32_t counts[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  hipError_t e = hipMemcpyAsync(counts, d_counts, nh * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  // order on the device first (sizes come from the device counts), then one
+  // wait for the counts, then the copy of the ordered records
+  fdas_cand* sorted = nullptr;
+  hipError_t e = fdas::launch_sort_candidates(d_cands, cap, nh, d_counts, p->rows, p->desc.z_max, p->bits_r,
+                                              p->d_sort_a, p->d_sort_b, p->d_sort_hist, p->d_sort_totals, &sorted, s);
+  if (e != hipSuccess) return hip_fail(e, "ordering candidates");
+  int32_t* counts = p->h_counts;
+  e = hipMemcpyAsync(counts, d_counts, nh * sizeof(int32_t), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "reading candidate counts");
   if (h_counts) std::copy(counts, counts + nh, h_counts);
   bool overflow = false;
-  fdas::PackPrefix pp{};
-  pp.nh = nh;
-  pp.off[0] = 0;
+  int off[9] = {0};
   for (int k = 0; k < nh; ++k) {
     if (counts[k] < 0) return fail(FDAS_ERR_DEVICE, "negative candidate count");
     if (counts[k] > cap) overflow = true;
-    pp.off[k + 1] = pp.off[k] + std::min(counts[k], cap);
+    off[k + 1] = off[k] + std::min(counts[k], cap);
   }
-  const int total = pp.off[nh];
-  fdas_cand* sorted = nullptr;
-  e = fdas::launch_sort_candidates(d_cands, cap, pp, p->rows, p->desc.z_max, p->bits_r, p->d_sort_a,
-                                   p->d_sort_b, p->d_sort_hist, &sorted, s);
-  if (e != hipSuccess) return hip_fail(e, "ordering candidates");
+  const int total = off[nh];
   int64_t nw = 0;
   if (p->desc.top_k <= 0) {
     nw = std::min<int64_t>(total, h_capacity);
@@ -381,7 +388,7 @@ fdas_status fdas_candidates(fdas_plan* p, const fdas_cand* d_cands, const int32_
     if (e != hipSuccess) return hip_fail(e, "reading candidates");
     std::vector<fdas_cand> keep;
     for (int k = 0; k < nh; ++k) {
-      std::vector<fdas_cand> v(all.begin() + pp.off[k], all.begin() + pp.off[k + 1]);
+      std::vector<fdas_cand> v(all.begin() + off[k], all.begin() + off[k + 1]);
       if ((int)v.size() > p->desc.top_k) {
         std::sort(v.begin(), v.end(), [](const fdas_cand& a, const fdas_cand& b) {
           if (a.power != b.power) return a.power > b.power;

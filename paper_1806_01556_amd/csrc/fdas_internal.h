@@ -80,20 +80,16 @@ hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, in
 
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s);
 
-// Offsets of the per-plane candidate lists inside the packed array:
-// plane k occupies [off[k], off[k+1]); off[nh] is the total.
-struct PackPrefix {
-  int nh;
-  int off[9];
-};
-
 int sort_tile_count(int m);
+int sort_passes(int rows, int bits_r);
 
-// Pack the per-plane lists (planes + k*cap, off[k+1]-off[k] records each)
-// into `a` and order them by (harm, z, r).  `b` is scratch of the same size,
-// `hist` holds 256 * sort_tile_count(total) ints.  *sorted receives a or b.
-hipError_t launch_sort_candidates(const fdas_cand* planes, int cap, const PackPrefix& pp, int rows, int z_max,
-                                  int bits_r, fdas_cand* a, fdas_cand* b, int* hist, fdas_cand** sorted,
-                                  hipStream_t s);
+// Pack the per-plane lists (planes + k*cap, min(counts[k], cap) records each,
+// counts read on the device) into `a` and order them by (harm, z, r).  `b` is
+// scratch of the same size (nh * cap records), `hist` holds
+// 256 * sort_tile_count(nh * cap) ints, `totals` 256 * sort_passes ints.
+// *sorted receives a or b.  Nothing waits for the host.
+hipError_t launch_sort_candidates(const fdas_cand* planes, int cap, int nh, const int32_t* counts, int rows,
+                                  int z_max, int bits_r, fdas_cand* a, fdas_cand* b, int* hist, int* totals,
+                                  fdas_cand** sorted, hipStream_t s);
 
 }  // namespace fdas

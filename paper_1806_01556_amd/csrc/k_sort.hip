@@ -5,11 +5,18 @@
 // by the key ((k-1)*rows + row) * 2^bits_r + r, which is unique per cell.
 // The lists are packed into one array and sorted by that key with an LSD
 // radix sort (8-bit digits, stable passes):
-//   k_sort_hist    per-tile digit histograms (tile = 4096 records)
-//   k_sort_scan    exclusive scan of the digit-major histogram table
-//   k_sort_scatter stable scatter: ranks within a tile come from wave
-//                  ballots (lanes with equal digits) plus per-wave counts
-// so the host only copies an already ordered array back.
+//   k_sort_pack    packs the per-plane lists (sizes read from the device
+//                  counts, so nothing waits for the host) and clears the
+//                  per-pass digit totals
+//   k_sort_hist    per-tile digit histograms (tile = 1024 records), and the
+//                  digit totals of the pass by atomics
+//   k_sort_scatter each tile forms its own output offsets (exclusive scan of
+//                  the digit totals + the same digit's counts in earlier
+//                  tiles), then scatters stably: ranks within a tile come
+//                  from wave ballots (lanes with equal digits) plus per-wave
+//                  counts
+// Every kernel is launched for the largest possible list (n_harm * capacity
+// records); tiles past the actual count return at once.
 
 #include "fdas_internal.h"
 
@@ -17,8 +24,8 @@ namespace fdas {
 namespace {
 
 constexpr int ST = 256;            // threads per block
-constexpr int SPT = 16;            // records per thread per tile
-constexpr int TILE = ST * SPT;     // 4096 records per tile
+constexpr int SPT = 4;             // records per thread per tile
+constexpr int TILE = ST * SPT;     // 1024 records per tile
 
 struct CandKey {
   int rows, z_max, bits_r;
@@ -29,22 +36,43 @@ __device__ __forceinline__ unsigned long long cand_key(const int4 c, const CandK
   return (slot << kp.bits_r) | (unsigned long long)(unsigned)c.z;
 }
 
-__global__ __launch_bounds__(ST) void k_sort_pack(const int4* __restrict__ planes, int cap, PackPrefix pp,
-                                                  int4* __restrict__ out) {
-  const int i = blockIdx.x * ST + threadIdx.x;
-  if (i >= pp.off[pp.nh]) return;
-  int k = 0;
-  while (k + 1 < pp.nh && i >= pp.off[k + 1]) ++k;
-  out[i] = planes[(size_t)k * cap + (i - pp.off[k])];
+// plane offsets of the packed array from the device counts (each plane keeps
+// at most cap records); returns the total
+__device__ __forceinline__ int pack_offsets(const int32_t* __restrict__ counts, int nh, int cap, int (&off)[9]) {
+  off[0] = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int c = k < nh ? min(max(counts[k], 0), cap) : 0;
+    off[k + 1] = off[k] + c;
+  }
+  return off[8];
 }
 
-__global__ __launch_bounds__(ST) void k_sort_hist(const int4* __restrict__ in, int m, int shift, CandKey kp,
-                                                  int* __restrict__ hist, int nblk) {
+__global__ __launch_bounds__(ST) void k_sort_pack(const int4* __restrict__ planes, int cap, int nh,
+                                                  const int32_t* __restrict__ counts, int4* __restrict__ out,
+                                                  int* __restrict__ totals, int ntotals) {
+  if (blockIdx.x == 0)
+    for (int t = threadIdx.x; t < ntotals; t += ST) totals[t] = 0;
+  int off[9];
+  const int m = pack_offsets(counts, nh, cap, off);
+  const int i = blockIdx.x * ST + threadIdx.x;
+  if (i >= m) return;
+  int k = 0;
+  while (k + 1 < nh && i >= off[k + 1]) ++k;
+  out[i] = planes[(size_t)k * cap + (i - off[k])];
+}
+
+__global__ __launch_bounds__(ST) void k_sort_hist(const int4* __restrict__ in, int cap, int nh,
+                                                  const int32_t* __restrict__ counts, int shift, CandKey kp,
+                                                  int* __restrict__ hist, int maxblk, int* __restrict__ totals) {
+  int off[9];
+  const int m = pack_offsets(counts, nh, cap, off);
+  if ((int)blockIdx.x * TILE >= m) return;  // uniform
   __shared__ int h[256];
   h[threadIdx.x] = 0;
   __syncthreads();
   const int base = blockIdx.x * TILE;
-#pragma unroll 4
+#pragma unroll
   for (int j = 0; j < SPT; ++j) {
     const int i = base + j * ST + threadIdx.x;
     if (i < m) {
@@ -53,41 +81,39 @@ __global__ __launch_bounds__(ST) void k_sort_hist(const int4* __restrict__ in, i
     }
   }
   __syncthreads();
-  hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+  const int v = h[threadIdx.x];
+  hist[threadIdx.x * maxblk + blockIdx.x] = v;
+  if (v) atomicAdd(&totals[threadIdx.x], v);
 }
 
-// Exclusive scan of `count` ints in place, one block of 1024 threads.
-__global__ __launch_bounds__(1024) void k_sort_scan(int* __restrict__ a, int count) {
-  __shared__ int part[1024];
-  const int t = threadIdx.x;
-  const int per = (count + 1023) / 1024;
-  const int lo = min(count, t * per), hi = min(count, lo + per);
-  int s = 0;
-  for (int i = lo; i < hi; ++i) s += a[i];
-  part[t] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    const int v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int run = part[t] - s;  // exclusive prefix of this thread's segment
-  for (int i = lo; i < hi; ++i) {
-    const int v = a[i];
-    a[i] = run;
-    run += v;
-  }
-}
-
-__global__ __launch_bounds__(ST) void k_sort_scatter(const int4* __restrict__ in, int4* __restrict__ out, int m,
-                                                     int shift, CandKey kp, const int* __restrict__ offs,
-                                                     int nblk) {
+__global__ __launch_bounds__(ST) void k_sort_scatter(const int4* __restrict__ in, int4* __restrict__ out, int cap,
+                                                     int nh, const int32_t* __restrict__ counts, int shift,
+                                                     CandKey kp, const int* __restrict__ hist, int maxblk,
+                                                     const int* __restrict__ totals) {
+  int off[9];
+  const int m = pack_offsets(counts, nh, cap, off);
+  if ((int)blockIdx.x * TILE >= m) return;  // uniform
   __shared__ int base[256];      // running position per digit inside this tile's output range
+  __shared__ int scan[256];
   __shared__ int wcnt[ST / 64][256];
   const int t = threadIdx.x;
   const int w = t >> 6;
-  base[t] = offs[t * nblk + blockIdx.x];
+  {
+    // records of digit t in earlier tiles, and the exclusive scan of the digit totals
+    int before = 0;
+    const int* hp = hist + (size_t)t * maxblk;
+    for (int b = 0; b < (int)blockIdx.x; ++b) before += hp[b];
+    const int tot = totals[t];
+    scan[t] = tot;
+    __syncthreads();
+    for (int o = 1; o < 256; o <<= 1) {
+      const int v = t >= o ? scan[t - o] : 0;
+      __syncthreads();
+      scan[t] += v;
+      __syncthreads();
+    }
+    base[t] = scan[t] - tot + before;
+  }
 #pragma unroll
   for (int q = 0; q < ST / 64; ++q) wcnt[q][t] = 0;
   __syncthreads();
@@ -136,26 +162,28 @@ __global__ __launch_bounds__(ST) void k_sort_scatter(const int4* __restrict__ in
 
 int sort_tile_count(int m) { return (m + TILE - 1) / TILE; }
 
-hipError_t launch_sort_candidates(const fdas_cand* planes, int cap, const PackPrefix& pp, int rows, int z_max,
-                                  int bits_r, fdas_cand* a, fdas_cand* b, int* hist, fdas_cand** sorted,
-                                  hipStream_t s) {
-  const int m = pp.off[pp.nh];
-  *sorted = a;
-  if (m == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sort_pack, dim3((m + ST - 1) / ST), dim3(ST), 0, s, reinterpret_cast<const int4*>(planes), cap,
-                     pp, reinterpret_cast<int4*>(a));
+int sort_passes(int rows, int bits_r) {
   const int slot_bits = 32 - __builtin_clz((unsigned)(8 * rows));  // covers (k-1)*rows + row < 8*rows
-  const int total_bits = slot_bits + bits_r;
-  const int passes = (total_bits + 7) / 8;
-  const int nblk = sort_tile_count(m);
+  return (slot_bits + bits_r + 7) / 8;
+}
+
+hipError_t launch_sort_candidates(const fdas_cand* planes, int cap, int nh, const int32_t* counts, int rows,
+                                  int z_max, int bits_r, fdas_cand* a, fdas_cand* b, int* hist, int* totals,
+                                  fdas_cand** sorted, hipStream_t s) {
+  const int maxm = nh * cap;
+  const int maxblk = sort_tile_count(maxm);
+  const int passes = sort_passes(rows, bits_r);
+  hipLaunchKernelGGL(k_sort_pack, dim3((maxm + ST - 1) / ST), dim3(ST), 0, s, reinterpret_cast<const int4*>(planes),
+                     cap, nh, counts, reinterpret_cast<int4*>(a), totals, 256 * passes);
   CandKey kp{rows, z_max, bits_r};
   int4* src = reinterpret_cast<int4*>(a);
   int4* dst = reinterpret_cast<int4*>(b);
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
-    hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(ST), 0, s, src, m, shift, kp, hist, nblk);
-    hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, hist, 256 * nblk);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(ST), 0, s, src, dst, m, shift, kp, hist, nblk);
+    int* tot = totals + 256 * p;
+    hipLaunchKernelGGL(k_sort_hist, dim3(maxblk), dim3(ST), 0, s, src, cap, nh, counts, shift, kp, hist, maxblk, tot);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(maxblk), dim3(ST), 0, s, src, dst, cap, nh, counts, shift, kp, hist,
+                       maxblk, tot);
     int4* tmp = src;
     src = dst;
     dst = tmp;
