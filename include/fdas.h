@@ -68,9 +68,15 @@ enum {
   FDAS_PREC_FP32 = 0
 };
 
-/* Harmonic index map used by fdas_harmonic_sum. */
+/* Harmonic index map used by fdas_harmonic_sum.  Algorithm 1 names a
+ * stretch() it does not define; STRETCH is the literal reading used by
+ * default, the other two follow the physics of a signal whose m-th harmonic
+ * sits at (m z, m r). */
 enum {
-  FDAS_HSUM_STRETCH = 0   /* SP_k(i, j) = FOP(trunc(i/k), floor(j/k)) */
+  FDAS_HSUM_STRETCH = 0,     /* HP_k = HP_{k-1} + FOP(trunc(i/k), floor(j/k)) */
+  FDAS_HSUM_FUNDAMENTAL = 1, /* HP_k = HP_{k-1} + FOP(k i, k j), 0 outside the plane */
+  FDAS_HSUM_HIGHEST = 2      /* HP_k = sum_{m<=k} FOP(rho(m i, k), rho(m j, k)), rho = nearest,
+                                halves away from zero; not cumulative */
 };
 
 typedef struct {
@@ -128,8 +134,9 @@ fdas_status fdas_convolve(fdas_plan* plan, const void* d_spectrum, int64_t n,
 
 /* Harmonic summing with threshold detection (Algorithm 1, Section 2.2):
  *   HP_1 = FOP, HP_k(i, j) = HP_{k-1}(i, j) + FOP(trunc(i/k), floor(j/k)),
- * summed in FP32 in k order; a cell with HP_k(i, j) > TA(k, i) is appended to
- * list k-1.  d_ta: float[n_harm][2*z_max+1] or NULL for the plan's default.
+ * summed in FP32 in k order (the plan's hsum_index selects another index map,
+ * see FDAS_HSUM_*; sums are then in m order); a cell with HP_k(i, j) > TA(k, i)
+ * is appended to list k-1.  d_ta: float[n_harm][2*z_max+1] or NULL for the plan's default.
  * d_cands: fdas_cand[n_harm][cand_capacity]; d_counts: int32[n_harm].
  * d_counts is reset by this call and ends holding the true number of cells
  * above threshold per plane, also when that exceeds cand_capacity (then only

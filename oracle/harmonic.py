@@ -22,6 +22,19 @@ Readings (the paper defines neither ``stretch`` nor TA):
   T_k = Q^{-1}(k, p_fa), Q the regularised upper incomplete gamma function.
   The default p_fa is 1e-6 per cell.
 * detection: strict HP_k(i, j) > TA(k, i); a candidate is (k, i, j, HP_k).
+
+Two further index maps (alternatives to the stretch reading, selected with
+``index``), both written from the physics of harmonically related signals: a
+pulsar whose fundamental sits at (z, r) has its m-th harmonic at (m z, m r).
+
+* "fundamental": plane k is anchored on the fundamental,
+  HP_k(i, j) = HP_{k-1}(i, j) + FOP(k i, k j), a term being 0 where (k i, k j)
+  lies outside the plane (|k i| > z_max or k j >= N).  Cumulative in k like
+  Algorithm 1.
+* "highest": plane k is anchored on the k-th (highest) harmonic,
+  HP_k(i, j) = sum_{m=1..k} FOP(rho(m i, k), rho(m j, k)), summed in m order,
+  rho(a, k) = a / k rounded to the nearest integer, halves away from zero.
+  Every index lies inside the plane; the planes are not cumulative.
   The list is given in (k, i, j) order, the loop order of Algorithm 1.
   Keeping only N_cand per plane is optional ("top_k"): the highest powers,
   ties broken by (i, j) ascending.
@@ -58,18 +71,63 @@ def stretch_plane(plane, k, cols=None):
     return plane[rows][:, src]
 
 
-def harmonic_planes(plane, n_harm=8, cols=None):
+def harmonic_planes(plane, n_harm=8, cols=None, index="stretch"):
     """Yield (k, HP_k) for k = 1..n_harm in the plane's own dtype.
 
     The sum is formed in k order, one rounding per step, exactly as
     HP_k = HP_{k-1} + SP_k; with a float32 plane this is the FP32 twin that a
     GPU kernel summing in the same order must reproduce bit for bit.
-    ``cols`` evaluates only those output columns.
+    ``cols`` evaluates only those output columns.  ``index`` selects the
+    index map: "stretch" (Algorithm 1 with the reading above), "fundamental"
+    or "highest" (see the module notes).
     """
+    if index == "fundamental":
+        yield from _planes_fundamental(plane, n_harm, cols)
+        return
+    if index == "highest":
+        yield from _planes_highest(plane, n_harm, cols)
+        return
+    if index != "stretch":
+        raise ValueError(f"unknown index map {index!r}")
     ncols = plane.shape[1] if cols is None else len(cols)
     hp = np.zeros((plane.shape[0], ncols), dtype=plane.dtype)
     for k in range(1, n_harm + 1):
         hp = hp + stretch_plane(plane, k, cols)
+        yield k, hp
+
+
+def _planes_fundamental(plane, n_harm, cols):
+    """HP_k = HP_{k-1} + FOP(k i, k j), zero outside the plane."""
+    rows, n = plane.shape
+    z_max = (rows - 1) // 2
+    j = np.arange(n, dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64)
+    i = np.arange(-z_max, z_max + 1, dtype=np.int64)
+    hp = np.zeros((rows, j.size), dtype=plane.dtype)
+    for k in range(1, n_harm + 1):
+        si, sj = k * i, k * j
+        ri, rj = np.abs(si) <= z_max, sj < n
+        sp = np.zeros_like(hp)
+        sp[np.ix_(ri, rj)] = plane[np.ix_(si[ri] + z_max, sj[rj])]
+        hp = hp + sp
+        yield k, hp
+
+
+def round_half_away(a, k):
+    """a / k rounded to the nearest integer, halves away from zero (integers)."""
+    a = np.asarray(a, dtype=np.int64)
+    return np.sign(a) * ((2 * np.abs(a) + k) // (2 * k))
+
+
+def _planes_highest(plane, n_harm, cols):
+    """HP_k = sum_{m=1..k} FOP(rho(m i, k), rho(m j, k)), in m order."""
+    rows, n = plane.shape
+    z_max = (rows - 1) // 2
+    j = np.arange(n, dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64)
+    i = np.arange(-z_max, z_max + 1, dtype=np.int64)
+    for k in range(1, n_harm + 1):
+        hp = np.zeros((rows, j.size), dtype=plane.dtype)
+        for m in range(1, k + 1):
+            hp = hp + plane[np.ix_(round_half_away(m * i, k) + z_max, round_half_away(m * j, k))]
         yield k, hp
 
 
@@ -84,7 +142,7 @@ def threshold_array(n_harm=8, z_max=42, p_fa=1e-6):
     return np.repeat(t[:, None], 2 * z_max + 1, axis=1)
 
 
-def candidates(plane, n_harm=8, ta=None, p_fa=1e-6, top_k=0, cols=None):
+def candidates(plane, n_harm=8, ta=None, p_fa=1e-6, top_k=0, cols=None, index="stretch"):
     """Candidate list of Algorithm 1 as a CAND_DTYPE array in (k, i, j) order.
 
     plane: FOP (rows = templates, columns = bins), float64 or float32.  With a
@@ -98,7 +156,7 @@ def candidates(plane, n_harm=8, ta=None, p_fa=1e-6, top_k=0, cols=None):
         ta = threshold_array(n_harm, z_max, p_fa)
     ta = np.asarray(ta, dtype=plane.dtype)
     out = []
-    for k, hp in harmonic_planes(plane, n_harm, cols):
+    for k, hp in harmonic_planes(plane, n_harm, cols, index):
         rows, cc = np.nonzero(hp > ta[k - 1][:, None])
         cols_k = colidx[cc]
         pw = hp[rows, cc].astype(np.float64)
@@ -122,7 +180,7 @@ def plane_counts(cands, n_harm=8):
     return np.bincount(cands["harm"] - 1, minlength=n_harm).astype(np.int64)
 
 
-def guard_cells(plane, n_harm=8, ta=None, p_fa=1e-6, rel=1e-4, cols=None):
+def guard_cells(plane, n_harm=8, ta=None, p_fa=1e-6, rel=1e-4, cols=None, index="stretch"):
     """Cells whose FP64 harmonic sum lies within rel*T of the threshold.
 
     Returned as a set of (k, z, r).  A correct FP32 implementation may report
@@ -134,7 +192,7 @@ def guard_cells(plane, n_harm=8, ta=None, p_fa=1e-6, rel=1e-4, cols=None):
     ta = np.asarray(ta, dtype=np.float64)
     colidx = np.arange(plane.shape[1], dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64)
     out = set()
-    for k, hp in harmonic_planes(np.asarray(plane, dtype=np.float64), n_harm, cols):
+    for k, hp in harmonic_planes(np.asarray(plane, dtype=np.float64), n_harm, cols, index):
         t = ta[k - 1][:, None]
         rows, cc = np.nonzero(np.abs(hp - t) <= rel * t)
         out.update((k, int(r) - z_max, int(colidx[c])) for r, c in zip(rows, cc))

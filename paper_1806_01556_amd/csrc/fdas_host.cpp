@@ -188,7 +188,9 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   if (desc->method != FDAS_CONV_AUTO && desc->method != FDAS_CONV_OLS_FFT && desc->method != FDAS_CONV_DIRECT)
     return fail(FDAS_ERR_INVALID_ARG, "unknown method %d", (int)desc->method);
   if (desc->precision != FDAS_PREC_FP32) return fail(FDAS_ERR_UNSUPPORTED, "precision %d is not built", (int)desc->precision);
-  if (desc->hsum_index != FDAS_HSUM_STRETCH) return fail(FDAS_ERR_UNSUPPORTED, "hsum_index %d is not built", (int)desc->hsum_index);
+  if (desc->hsum_index != FDAS_HSUM_STRETCH && desc->hsum_index != FDAS_HSUM_FUNDAMENTAL &&
+      desc->hsum_index != FDAS_HSUM_HIGHEST)
+    return fail(FDAS_ERR_INVALID_ARG, "unknown hsum_index %d", (int)desc->hsum_index);
   if (desc->ols_chunk != 0 && desc->ols_chunk != fdas::kOlsC)
     return fail(FDAS_ERR_UNSUPPORTED, "ols_chunk %d: only %d is built", (int)desc->ols_chunk, fdas::kOlsC);
 
@@ -336,7 +338,7 @@ fdas_status fdas_harmonic_sum(fdas_plan* p, const float* d_fop, int64_t n, int64
   if (e != hipSuccess) return hip_fail(e, "clearing the candidate counts");
   fdas::HsWork wk{it->second.first, it->second.second, p->d_hitrows, p->d_hitrow_count};
   e = fdas::launch_harmsum(d_fop, n, ld, p->desc.z_max, p->desc.n_harm, d_ta ? d_ta : p->d_ta, d_cands,
-                           p->desc.cand_capacity, d_counts, wk, s);
+                           p->desc.cand_capacity, d_counts, wk, p->desc.hsum_index, s);
   if (e != hipSuccess) return hip_fail(e, "launching the harmonic sum");
   return ok();
 }

@@ -74,9 +74,10 @@ struct HsWork {
   int32_t* hitrow_count;     // entries appended by phase 1
 };
 
+// index: FDAS_HSUM_* (the stretch map uses the two-phase kernels for 85 rows)
 hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, int n_harm,
                           const float* ta, fdas_cand* cands, int cap, int32_t* counts,
-                          const HsWork& wk, hipStream_t s);
+                          const HsWork& wk, int index, hipStream_t s);
 
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s);
 

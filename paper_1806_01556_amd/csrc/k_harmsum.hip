@@ -98,6 +98,93 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum(const float* __restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Alternative index maps (plan option hsum_index), any row count.  A pulsar
+// whose fundamental sits at (z, r) has its m-th harmonic at (m z, m r).
+//
+// Fundamental-anchored: HP_k(i, j) = HP_{k-1}(i, j) + FOP(k i, k j), a term
+// being 0 where (k i, k j) is outside the plane.  Cumulative in k.
+template <int NH>
+__global__ __launch_bounds__(HS_THREADS) void k_harmsum_fund(const float* __restrict__ fop, int64_t ld, int n,
+                                                             int z_max, const float* __restrict__ ta,
+                                                             fdas_cand* __restrict__ cands, int cap,
+                                                             int32_t* __restrict__ counts) {
+  const int64_t g = (int64_t)blockIdx.x * HS_THREADS + threadIdx.x;
+  const int64_t j0 = g * 4;
+  if (j0 >= n) return;
+  const int rows = 2 * z_max + 1;
+  for (int r = 0; r < rows; ++r) {
+    const int i = r - z_max;
+    const float* row = fop + (size_t)r * ld;
+    float hp[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) hp[a] = (j0 + a < n) ? row[j0 + a] : 0.0f;
+    {
+      const float t = ta[r];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (hp[a] > t && j0 + a < n) emit(1, i, (int)(j0 + a), hp[a], cands, cap, counts);
+    }
+#pragma unroll
+    for (int m = 2; m <= NH; ++m) {
+      const int si = m * i;
+      const bool rin = si >= -z_max && si <= z_max;
+      const float* src = fop + (size_t)(rin ? si + z_max : 0) * ld;
+      const float t = ta[(m - 1) * rows + r];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int64_t sj = (int64_t)m * (j0 + a);
+        const float v = (rin && sj < n) ? src[sj] : 0.0f;
+        hp[a] = hp[a] + v;
+        if (hp[a] > t && j0 + a < n) emit(m, i, (int)(j0 + a), hp[a], cands, cap, counts);
+      }
+    }
+  }
+}
+
+// a / k rounded to the nearest integer, halves away from zero
+__device__ __forceinline__ int64_t round_div(int64_t a, int k) {
+  return a >= 0 ? (2 * a + k) / (2 * k) : -((-2 * a + k) / (2 * k));
+}
+
+// Highest-harmonic-anchored: HP_k(i, j) = sum_{m=1..k} FOP(rho(m i, k), rho(m j, k)),
+// summed in m order, rho = rounding to the nearest integer with halves away
+// from zero.  Every index is inside the plane; the planes are not cumulative.
+template <int NH>
+__global__ __launch_bounds__(HS_THREADS) void k_harmsum_high(const float* __restrict__ fop, int64_t ld, int n,
+                                                             int z_max, const float* __restrict__ ta,
+                                                             fdas_cand* __restrict__ cands, int cap,
+                                                             int32_t* __restrict__ counts) {
+  const int64_t g = (int64_t)blockIdx.x * HS_THREADS + threadIdx.x;
+  const int64_t j0 = g * 4;
+  if (j0 >= n) return;
+  const int rows = 2 * z_max + 1;
+  // columns past n - 1 (the ragged last group) read column n - 1 and are never emitted
+  int64_t jj[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) jj[a] = j0 + a < n ? j0 + a : n - 1;
+  for (int r = 0; r < rows; ++r) {
+    const int i = r - z_max;
+#pragma unroll
+    for (int k = 1; k <= NH; ++k) {
+      float hp[4];
+#pragma unroll
+      for (int m = 1; m <= k; ++m) {
+        const float* src = fop + (size_t)(round_div((int64_t)m * i, k) + z_max) * ld;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const float v = src[round_div((int64_t)m * jj[a], k)];
+          hp[a] = m == 1 ? v : hp[a] + v;
+        }
+      }
+      const float t = ta[(k - 1) * rows + r];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        if (hp[a] > t && j0 + a < n) emit(k, i, (int)(j0 + a), hp[a], cands, cap, counts);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fast path for a compile-time row count (2*Z+1 rows), in two phases.
 //
 // Phase 1 (k_harmsum_z): each thread owns 4 adjacent columns and walks all
@@ -354,7 +441,35 @@ hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s) 
 }
 
 hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, int n_harm, const float* ta,
-                          fdas_cand* cands, int cap, int32_t* counts, const HsWork& wk, hipStream_t s) {
+                          fdas_cand* cands, int cap, int32_t* counts, const HsWork& wk, int index, hipStream_t s) {
+  if (index == FDAS_HSUM_FUNDAMENTAL || index == FDAS_HSUM_HIGHEST) {
+    const int64_t groups = (n + 3) / 4;
+    const unsigned blocks = (unsigned)((groups + HS_THREADS - 1) / HS_THREADS);
+    const bool fund = index == FDAS_HSUM_FUNDAMENTAL;
+    switch (n_harm) {
+#define FDAS_HSX_CASE(NH)                                                                                      \
+  case NH:                                                                                                     \
+    if (fund)                                                                                                  \
+      hipLaunchKernelGGL(k_harmsum_fund<NH>, dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max, ta, \
+                         cands, cap, counts);                                                                  \
+    else                                                                                                       \
+      hipLaunchKernelGGL(k_harmsum_high<NH>, dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max, ta, \
+                         cands, cap, counts);                                                                  \
+    break;
+      FDAS_HSX_CASE(1)
+      FDAS_HSX_CASE(2)
+      FDAS_HSX_CASE(3)
+      FDAS_HSX_CASE(4)
+      FDAS_HSX_CASE(5)
+      FDAS_HSX_CASE(6)
+      FDAS_HSX_CASE(7)
+      FDAS_HSX_CASE(8)
+#undef FDAS_HSX_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const int nn = (int)n;
   if (z_max == 42) {
     // two-phase fast path for the 85-template plane

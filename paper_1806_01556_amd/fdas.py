@@ -23,7 +23,7 @@ STATUS_NAMES = {
 }
 CONV_AUTO, CONV_OLS_FFT, CONV_DIRECT = 0, 1, 2
 PREC_FP32 = 0
-HSUM_STRETCH = 0
+HSUM_STRETCH, HSUM_FUNDAMENTAL, HSUM_HIGHEST = 0, 1, 2
 
 #: symbols declared in include/fdas.h
 EXPORTED = (
