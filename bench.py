@@ -90,6 +90,91 @@ def cpu_baseline(spec, n_full):
     }
 
 
+def bench_batch(args, torch, fdas, synth, dev):
+    """Batched dispersion trials: `trials` spectra of lengths drawn from
+    {2^20, 2^21, 3*2^20, 2^22} (seeds 3000 + b, 0-4 pulsars each) per step,
+    through fdas_search_batch + fdas_candidates_batch with the autotuned
+    launch parameters; the same spectra through the single-spectrum calls
+    are timed for comparison."""
+    T = args.trials
+    t_syn = time.perf_counter()
+    specs = [synth.batch_member(b)[0] for b in range(T)]
+    t_syn = time.perf_counter() - t_syn
+    lens = [s.shape[0] for s in specs]
+    n_max = max(lens)
+    plan = fdas.plan_create(n_max=n_max)
+    xs = [torch.from_numpy(s).to(dev) for s in specs]
+    del specs
+    fops = [torch.empty((plan.rows, fdas.fop_ld(n)), dtype=torch.float32, device=dev) for n in lens]
+    bufs = [fdas.alloc_cands(plan, dev) for _ in lens]
+    trials = fdas.trials_array([(x, n, f, f.shape[1], c[0], c[1]) for x, n, f, c in zip(xs, lens, fops, bufs)])
+    stream = torch.cuda.current_stream()
+    t_tune = time.perf_counter()
+    tuning = fdas.autotune(plan, trials, repeats=2, stream=stream)
+    t_tune = time.perf_counter() - t_tune
+
+    def step():
+        fdas.search_batch(plan, trials, stream=stream)
+        return fdas.candidates_batch(plan, trials, stream=stream, allow_overflow=True, copy=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    gpu_ms = 0.0
+    for _ in range(args.steps):
+        e0.record(stream)
+        fdas.search_batch(plan, trials, stream=stream)
+        e1.record(stream)
+        cands, counts = fdas.candidates_batch(plan, trials, stream=stream, allow_overflow=True, copy=False)
+        gpu_ms += e0.elapsed_time(e1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+
+    # the same trials one spectrum at a time through the single-spectrum calls
+    single_steps = max(1, min(args.steps, 3))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(single_steps):
+        for x, n, f, (c, k) in zip(xs, lens, fops, bufs):
+            fdas.convolve(plan, x, f, n=n, stream=stream)
+            fdas.harmonic_sum(plan, f, n, c, k, stream=stream)
+            fdas.candidates(plan, c, k, stream=stream, allow_overflow=True, copy=False)
+    torch.cuda.synchronize()
+    single_ms = 1e3 * (time.perf_counter() - t1) / single_steps
+
+    bins = int(sum(lens))
+    hbm_bytes = 688 * bins                         # 8 + 340 B/bin conv, 340 B/bin harmonic sum
+    out = {
+        "metric": "FDAS spectra/s, batch of dispersion trials (uneven lengths, 85 templates, 8 harmonics)",
+        "value": round(T * args.steps / wall, 3),
+        "unit": "spectra/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batch_{T}_trials", "trials": T, "lengths": sorted(set(lens)),
+                   "total_bins": bins, "templates": 85, "harmonics": 8, "seeds": "3000+b",
+                   "tuning": tuning},
+        "batch_gpu_ms_per_step": round(gpu_ms / args.steps, 3),
+        "batch_hbm_gbs_algorithmic": round(hbm_bytes / (gpu_ms / args.steps * 1e-3) / 1e9, 1),
+        "single_calls_ms_per_step": round(single_ms, 3),
+        "single_calls_spectra_per_s": round(T / (single_ms * 1e-3), 3),
+        "batch_speedup_vs_single_calls": round(single_ms / ms_per_step, 3),
+        "candidates": int(sum(c.size for c in cands)),
+        "setup_s": {"synthesis": round(t_syn, 1), "autotune": round(t_tune, 1)},
+    }
+    plan.destroy()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +190,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy the FOP buffer 3 times (a plain copy of known size, "
                          "so HBM counters can be scaled to bytes)")
+    ap.add_argument("--workload", choices=("ska", "batch"), default="ska",
+                    help="ska: one 2^22-bin spectrum per step (the headline); batch: 64 dispersion trials of "
+                         "uneven length per step through the batch calls")
+    ap.add_argument("--trials", type=int, default=64, help="batch workload: trials per step")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -121,6 +210,8 @@ def main():
         sys.exit(1)
     dev = torch.device("cuda:0")
     fdas.lib()  # raises if libfdas.so is missing
+    if args.workload == "batch":
+        return bench_batch(args, torch, fdas, synth, dev)
 
     n = 1 << 22
     spec, pulsars = synth.ska(n=n, seed=2)

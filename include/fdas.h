@@ -158,6 +158,63 @@ fdas_status fdas_candidates(fdas_plan* plan, const fdas_cand* d_cands, const int
                             fdas_cand* h_out, int64_t h_capacity, int64_t* h_n,
                             int32_t* h_counts, void* stream);
 
+/* --- batches of dispersion trials ------------------------------------------
+ * A beam yields one spectrum per dispersion-measure trial (Table 1),
+ * searched independently.  The batch calls run the same two steps as
+ * fdas_convolve + fdas_harmonic_sum (identical arithmetic, so identical
+ * results) for many spectra of uneven length at once: one persistent
+ * convolution launch works through a queue of (trial, chunk, template group)
+ * items, one harmonic-sum launch covers every trial's column tiles, and the
+ * sequence is replayed from a HIP graph.  Trials can be split into groups
+ * whose harmonic sums overlap the next group's convolution (the pipeline
+ * computing of Section 3.3, with one FOP buffer per trial). */
+
+/* One trial of a batch.  All pointers are caller-owned device memory; the FOP,
+ * candidate and count buffers of different trials of one call must not
+ * overlap.  Layout rules as for fdas_convolve / fdas_harmonic_sum. */
+typedef struct {
+  const void* d_spectrum; /* complex64[n] */
+  int64_t n;              /* 1 <= n <= n_max */
+  float* d_fop;           /* [2*z_max+1][ld] */
+  int64_t ld;             /* >= n, multiple of 4 */
+  fdas_cand* d_cands;     /* [n_harm][cand_capacity] */
+  int32_t* d_counts;      /* [n_harm], reset by the call */
+} fdas_trial;
+
+/* Launch parameters chosen by fdas_autotune (all fields 0 = built-in default). */
+typedef struct {
+  int32_t conv_templates_per_item; /* templates sharing one forward FFT (1..2*z_max+1) */
+  int32_t conv_workgroups_per_cu;  /* resident convolution workgroups per compute unit (1..2) */
+  int32_t overlap_groups;          /* trial groups whose harmonic sums overlap later convolutions (1..8) */
+  int32_t emit_workgroups;         /* workgroups of the candidate-emission pass (64..16384) */
+} fdas_tuning;
+
+/* Convolution + harmonic sum (default thresholds) of `count` trials,
+ * asynchronous on `stream`.  1 <= count <= 1024.  Equivalent to calling
+ * fdas_convolve and fdas_harmonic_sum for each trial in turn.  The first call
+ * with a new batch shape records a HIP graph (this call then synchronises);
+ * later calls with the same shape replay it. */
+fdas_status fdas_search_batch(fdas_plan* plan, const fdas_trial* h_trials, int32_t count, void* stream);
+
+/* Ordered candidates of every trial of a batch in one readback: records of
+ * trial t occupy h_out[h_offsets[t] .. h_offsets[t+1]) in (harm, z, r) order.
+ * h_offsets: int64[count + 1]; h_counts (optional): int32[count][n_harm], the
+ * device counts.  top_k applies per trial and plane.  Synchronises.  Returns
+ * FDAS_ERR_CAPACITY if a device list overflowed or h_capacity was too small
+ * (the records returned are then ordered but incomplete). */
+fdas_status fdas_candidates_batch(fdas_plan* plan, const fdas_trial* h_trials, int32_t count, fdas_cand* h_out,
+                                  int64_t h_capacity, int64_t* h_offsets, int32_t* h_counts, void* stream);
+
+/* Time the batch path on these trials (their buffers are overwritten) over a
+ * set of launch parameters, keep the fastest in the plan for later batch
+ * calls, and report it in *out (optional).  `repeats` timed runs per
+ * setting (>= 1).  Synchronises. */
+fdas_status fdas_autotune(fdas_plan* plan, const fdas_trial* h_trials, int32_t count, int32_t repeats,
+                          fdas_tuning* out, void* stream);
+
+/* Set the launch parameters of the batch path by hand (NULL = defaults). */
+fdas_status fdas_set_tuning(fdas_plan* plan, const fdas_tuning* tuning);
+
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* fdas_last_error(void);
 

@@ -10,41 +10,12 @@
 #include <string>
 #include <vector>
 
-#include "fdas_internal.h"
+#include "fdas_plan.h"
 
-struct fdas_plan {
-  fdas_plan_desc desc;
-  int device = 0;
-  int rows = 0;          // 2*z_max + 1
-  int L_max = 0;         // taps of the longest template
-  fdas::OlsGeom geom{};  // overlap-save chunk geometry
-  int conv_slots = 512;  // resident convolution workgroups (2 per compute unit)
-  bool direct = false;      // FDAS_CONV_DIRECT: matrix-core correlation instead of overlap-save
-  float* d_Bpk = nullptr;   // direct: packed template operand
-  int4* d_dtiles = nullptr; // direct: per-tile {P, first pair, members, 0}
-  int* d_drows = nullptr;   // direct: [tiles][8] FOP rows
-  int dtiles = 0, dP_max = 0, dP8_max = 0;
-  float2* d_H = nullptr;    // [rows][C] template spectra
-  float2* d_tw1 = nullptr;  // [16][256]
-  float2* d_tw2 = nullptr;  // [16][16]
-  float* d_ta = nullptr;    // [n_harm][rows] default thresholds
-  std::vector<float> h_ta;
-  fdas_cand* d_sort_a = nullptr;  // [n_harm * cand_capacity] packed candidates
-  fdas_cand* d_sort_b = nullptr;  // radix-sort ping-pong buffer
-  int* d_sort_hist = nullptr;     // [256 * tiles] digit histograms
-  int* d_sort_totals = nullptr;   // [256 * passes] digit totals per pass
-  int32_t* h_counts = nullptr;    // pinned host copy of the device counts
-  int bits_r = 1;                 // bits of the column index in the sort key
-  std::map<int64_t, std::pair<int*, int>> tile_orders;  // n -> (device tile order, workgroups)
-  int4* d_hitrows = nullptr;      // [ceil(n_max/4)] rows with hits (harmonic sum phase 1)
-  int32_t* d_hitrow_count = nullptr;
-};
-
-namespace {
+namespace fdas {
 
 thread_local std::string g_err;
 
-fdas_status fail(fdas_status s, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 fdas_status fail(fdas_status s, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -65,23 +36,6 @@ fdas_status hip_fail(hipError_t e, const char* what) {
   return fail(FDAS_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-// Make the plan's device current for the duration of a call.
-struct DeviceGuard {
-  int prev = -1;
-  bool changed = false;
-  hipError_t err = hipSuccess;
-  explicit DeviceGuard(int dev) {
-    err = hipGetDevice(&prev);
-    if (err == hipSuccess && prev != dev) {
-      err = hipSetDevice(dev);
-      changed = err == hipSuccess;
-    }
-  }
-  ~DeviceGuard() {
-    if (changed) (void)hipSetDevice(prev);
-  }
-};
-
 void free_plan(fdas_plan* p) {
   if (!p) return;
   if (p->d_Bpk) (void)hipFree(p->d_Bpk);
@@ -99,6 +53,7 @@ void free_plan(fdas_plan* p) {
   for (auto& kv : p->tile_orders) (void)hipFree(kv.second.first);
   if (p->d_hitrows) (void)hipFree(p->d_hitrows);
   if (p->d_hitrow_count) (void)hipFree(p->d_hitrow_count);
+  free_batch(p);
   delete p;
 }
 
@@ -122,7 +77,48 @@ fdas_status check_fop_args(const fdas_plan* p, const void* fop, int64_t n, int64
   return FDAS_OK;
 }
 
-}  // namespace
+void keep_top_k(const fdas_cand* sorted, const int* off, int nh, int top_k, std::vector<fdas_cand>& keep) {
+  // each plane keeps its top_k powers (ties: lower z, then lower r), in (z, r) order
+  for (int k = 0; k < nh; ++k) {
+    std::vector<fdas_cand> v(sorted + off[k], sorted + off[k + 1]);
+    if ((int)v.size() > top_k) {
+      std::sort(v.begin(), v.end(), [](const fdas_cand& a, const fdas_cand& b) {
+        if (a.power != b.power) return a.power > b.power;
+        if (a.z != b.z) return a.z < b.z;
+        return a.r < b.r;
+      });
+      v.resize(top_k);
+      std::sort(v.begin(), v.end(), [](const fdas_cand& a, const fdas_cand& b) {
+        if (a.z != b.z) return a.z < b.z;
+        return a.r < b.r;
+      });
+    }
+    keep.insert(keep.end(), v.begin(), v.end());
+  }
+}
+
+hipError_t tile_order_for(fdas_plan* p, int64_t n, const int** d_order, int* blocks) {
+  auto it = p->tile_orders.find(n);
+  if (it == p->tile_orders.end()) {
+    std::vector<int> order;
+    harmsum_tile_order(n, order);
+    int* d = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&d), order.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(d, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      if (d) (void)hipFree(d);
+      return e;
+    }
+    it = p->tile_orders.emplace(n, std::make_pair(d, (int)order.size())).first;
+  }
+  *d_order = it->second.first;
+  *blocks = it->second.second;
+  return hipSuccess;
+}
+
+}  // namespace fdas
+
+using namespace fdas;
 
 extern "C" {
 
@@ -322,21 +318,15 @@ fdas_status fdas_harmonic_sum(fdas_plan* p, const float* d_fop, int64_t n, int64
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
   // workgroup -> column-tile order of the 85-row kernel, built once per spectrum length
-  auto it = p->tile_orders.find(n);
-  if (it == p->tile_orders.end()) {
-    std::vector<int> order;
-    fdas::harmsum_tile_order(n, order);
-    int* d_order = nullptr;
-    hipError_t e0 = upload(&d_order, order.data(), order.size() * sizeof(int));
-    if (e0 != hipSuccess) {
-      if (d_order) (void)hipFree(d_order);
-      return hip_fail(e0, "uploading the harmonic-sum tile order");
-    }
-    it = p->tile_orders.emplace(n, std::make_pair(d_order, (int)order.size())).first;
+  const int* d_order = nullptr;
+  int order_blocks = 0;
+  {
+    hipError_t e0 = fdas::tile_order_for(p, n, &d_order, &order_blocks);
+    if (e0 != hipSuccess) return hip_fail(e0, "uploading the harmonic-sum tile order");
   }
   hipError_t e = fdas::launch_fill_i32(d_counts, p->desc.n_harm, 0, s);
   if (e != hipSuccess) return hip_fail(e, "clearing the candidate counts");
-  fdas::HsWork wk{it->second.first, it->second.second, p->d_hitrows, p->d_hitrow_count};
+  fdas::HsWork wk{d_order, order_blocks, p->d_hitrows, p->d_hitrow_count, p->tuning.emit_workgroups};
   e = fdas::launch_harmsum(d_fop, n, ld, p->desc.z_max, p->desc.n_harm, d_ta ? d_ta : p->d_ta, d_cands,
                            p->desc.cand_capacity, d_counts, wk, p->desc.hsum_index, s);
   if (e != hipSuccess) return hip_fail(e, "launching the harmonic sum");
@@ -389,22 +379,7 @@ fdas_status fdas_candidates(fdas_plan* p, const fdas_cand* d_cands, const int32_
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "reading candidates");
     std::vector<fdas_cand> keep;
-    for (int k = 0; k < nh; ++k) {
-      std::vector<fdas_cand> v(all.begin() + off[k], all.begin() + off[k + 1]);
-      if ((int)v.size() > p->desc.top_k) {
-        std::sort(v.begin(), v.end(), [](const fdas_cand& a, const fdas_cand& b) {
-          if (a.power != b.power) return a.power > b.power;
-          if (a.z != b.z) return a.z < b.z;
-          return a.r < b.r;
-        });
-        v.resize(p->desc.top_k);
-        std::sort(v.begin(), v.end(), [](const fdas_cand& a, const fdas_cand& b) {
-          if (a.z != b.z) return a.z < b.z;
-          return a.r < b.r;
-        });
-      }
-      keep.insert(keep.end(), v.begin(), v.end());
-    }
+    keep_top_k(all.data(), off, nh, p->desc.top_k, keep);
     nw = std::min<int64_t>((int64_t)keep.size(), h_capacity);
     if (nw > 0) std::memcpy(h_out, keep.data(), (size_t)nw * sizeof(fdas_cand));
     if (nw < (int64_t)keep.size()) overflow = true;

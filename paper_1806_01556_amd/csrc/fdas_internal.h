@@ -45,6 +45,24 @@ hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld,
                            const float2* H, const float2* tw1, const float2* tw2,
                            int rows, const OlsGeom& g, int slots, hipStream_t s);
 
+// Templates sharing one forward FFT, chosen by a cost model for a queue of
+// items_per_template chunks run on `slots` resident workgroups.
+int ols_templates_per_item(int64_t items_per_template, int rows, int slots);
+
+// One spectrum of a batch for the convolution queue (device table entry).
+struct ConvTrial {
+  const float2* x;
+  float* fop;
+  int64_t n;
+  int64_t ld;
+  int64_t item0;  // first queue item of this trial
+};
+
+// Queue items [item_begin, item_end) of a batch; tpg templates per item.
+hipError_t launch_ols_conv_batch(const ConvTrial* trials, int ntrials, int64_t item_begin, int64_t item_end,
+                                 const float2* H, const float2* tw1, const float2* tw2, int rows, int tpg,
+                                 const OlsGeom& g, int slots, hipStream_t s);
+
 struct DirectTables {
   const float* Bpk;    // packed template operand
   const int4* tiles;   // per tile {P, first pair, members, padded pairs}
@@ -72,7 +90,29 @@ struct HsWork {
   int blocks;                // workgroups of phase 1
   int4* hitrows;             // {j0, row mask words}: ceil(n/4) entries at most
   int32_t* hitrow_count;     // entries appended by phase 1
+  int emit_blocks;           // workgroups of phase 2 (0: default)
 };
+
+// One spectrum of a batch for the harmonic sum (device table entry).
+struct HsTrial {
+  const float* fop;
+  int64_t ld;
+  fdas_cand* cands;
+  int32_t* counts;
+  const int* tile_of_block;  // this length's tile order
+  int n;
+  int block0;                // first phase-1 workgroup of this trial
+  int nblocks;               // phase-1 workgroups of this trial
+  int pad;
+};
+
+hipError_t launch_zero_counts_batch(const HsTrial* trials, int ntrials, int nh, hipStream_t s);
+
+// Two-phase 85-row stretch sum over phase-1 workgroups [blk_begin, blk_end)
+// of a batch (default thresholds ta, capacity cap per plane).
+hipError_t launch_harmsum_batch85(const HsTrial* trials, int ntrials, int blk_begin, int blk_end, int n_harm,
+                                  const float* ta, int cap, int4* hitrows, int32_t* hitrow_count, int eblocks,
+                                  hipStream_t s);
 
 // index: FDAS_HSUM_* (the stretch map uses the two-phase kernels for 85 rows)
 hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, int n_harm,
@@ -83,6 +123,9 @@ hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s);
 
 int sort_tile_count(int m);
 int sort_passes(int rows, int bits_r);
+
+// out[t * nh + k] = ptrs[t][k] for t < count, k < nh
+hipError_t launch_gather_counts(int32_t* const* ptrs, int count, int nh, int32_t* out, hipStream_t s);
 
 // Pack the per-plane lists (planes + k*cap, min(counts[k], cap) records each,
 // counts read on the device) into `a` and order them by (harm, z, r).  `b` is

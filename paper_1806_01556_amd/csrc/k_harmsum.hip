@@ -321,6 +321,49 @@ __device__ __forceinline__ void hs_prologue(HsState<NH>& st, const float* __rest
 // ld >= n and ld % 4 == 0; a source column j/k + 1 read for k >= 2 is at most
 // (n-1)/2 + 1 <= ld - 1.  Values read beyond column n - 1 only reach columns
 // >= n, which phase 2 never emits.
+// Phase 1 for one thread: columns j0..j0+3 of a plane with n columns.
+// Returns the bit mask of rows holding a cell above threshold (3 words).
+template <int Z, int NH>
+__device__ __forceinline__ void hs_phase1_thread(const float* __restrict__ fop, int64_t ld, int j0,
+                                                 const float* __restrict__ s_ta, unsigned (&mask)[3]) {
+  int lo[NH + 1], rmod[NH + 1];
+#pragma unroll
+  for (int m = 0; m <= NH; ++m) {
+    lo[m] = m >= 2 ? j0 / m : 0;
+    rmod[m] = m >= 2 ? j0 - lo[m] * m : 0;
+  }
+  HsState<NH> st;
+  st.hitmask[0] = st.hitmask[1] = st.hitmask[2] = 0u;
+  hs_prologue<Z, NH, 0>(st, fop, ld, j0, lo);
+  hs_rows<Z, NH, 0>(st, fop, ld, j0, lo, rmod, s_ta);
+  mask[0] = st.hitmask[0];
+  mask[1] = st.hitmask[1];
+  mask[2] = st.hitmask[2];
+}
+
+template <int Z, int NH>
+__device__ __forceinline__ void hs_load_ta(const float* __restrict__ ta, float* __restrict__ s_ta) {
+  constexpr int ROWS = 2 * Z + 1;
+  for (int e = threadIdx.x; e < ROWS * 8; e += HS_THREADS) {
+    const int r = e / 8, m = e % 8;
+    s_ta[e] = m < NH ? ta[m * ROWS + r] : 0.0f;
+  }
+}
+
+// Append this block's entries {j0, mask words} to the global hit-row list.
+__device__ __forceinline__ void hs_flush_entries(const int4* __restrict__ s_ent, int cnt, int* s_base,
+                                                 int4* __restrict__ hitrows, int32_t* __restrict__ hitrow_count) {
+  if (cnt == 0) return;  // uniform
+  if (threadIdx.x == 0) *s_base = atomicAdd(hitrow_count, cnt);
+  __syncthreads();
+  if (threadIdx.x < cnt) hitrows[*s_base + threadIdx.x] = s_ent[threadIdx.x];
+}
+
+// Phase 1 over all columns [0, n) in groups of 4 (the last group may be
+// partial).  The 16-byte read of the last group stays inside the row because
+// ld >= n and ld % 4 == 0; a source column j/k + 1 read for k >= 2 is at most
+// (n-1)/2 + 1 <= ld - 1.  Values read beyond column n - 1 only reach columns
+// >= n, which phase 2 never emits.
 template <int Z, int NH>
 __global__ __launch_bounds__(HS_THREADS) void k_harmsum_z(const float* __restrict__ fop, int64_t ld, int n,
                                                           const int* __restrict__ tile_of_block,
@@ -331,10 +374,7 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_z(const float* __restric
   __shared__ float s_ta[ROWS * 8];  // [row][k-1]
   __shared__ int4 s_ent[HS_THREADS];
   __shared__ int s_nent, s_base;
-  for (int e = threadIdx.x; e < ROWS * 8; e += HS_THREADS) {
-    const int r = e / 8, m = e % 8;
-    s_ta[e] = m < NH ? ta[m * ROWS + r] : 0.0f;
-  }
+  hs_load_ta<Z, NH>(ta, s_ta);
   if (threadIdx.x == 0) s_nent = 0;
   __syncthreads();
   const int groups = (n + 3) / 4;
@@ -342,27 +382,104 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_z(const float* __restric
   const int g = tile * HS_THREADS + threadIdx.x;
   if (tile >= 0 && g < groups) {
     const int j0 = 4 * g;
-    int lo[NH + 1], rmod[NH + 1];
-#pragma unroll
-    for (int m = 0; m <= NH; ++m) {
-      lo[m] = m >= 2 ? j0 / m : 0;
-      rmod[m] = m >= 2 ? j0 - lo[m] * m : 0;
-    }
-    HsState<NH> st;
-    st.hitmask[0] = st.hitmask[1] = st.hitmask[2] = 0u;
-    hs_prologue<Z, NH, 0>(st, fop, ld, j0, lo);
-    hs_rows<Z, NH, 0>(st, fop, ld, j0, lo, rmod, s_ta);
-    if (st.hitmask[0] | st.hitmask[1] | st.hitmask[2]) {
+    unsigned mask[3];
+    hs_phase1_thread<Z, NH>(fop, ld, j0, s_ta, mask);
+    if (mask[0] | mask[1] | mask[2]) {
       const int pos = atomicAdd(&s_nent, 1);
-      s_ent[pos] = make_int4(j0, (int)st.hitmask[0], (int)st.hitmask[1], (int)st.hitmask[2]);
+      s_ent[pos] = make_int4(j0, (int)mask[0], (int)mask[1], (int)mask[2]);
     }
   }
   __syncthreads();
-  const int cnt = s_nent;
-  if (cnt == 0) return;  // uniform
-  if (threadIdx.x == 0) s_base = atomicAdd(hitrow_count, cnt);
+  hs_flush_entries(s_ent, s_nent, &s_base, hitrows, hitrow_count);
+}
+
+// Batch form: workgroup blk_begin + blockIdx.x belongs to the last trial whose
+// block0 is <= it; its tile comes from that trial's tile order.  Entries carry
+// the trial in bits 21..31 of the third mask word (rows 64..84 use bits 0..20).
+template <int Z, int NH>
+__global__ __launch_bounds__(HS_THREADS) void k_harmsum_z_batch(const HsTrial* __restrict__ trials, int ntrials,
+                                                                int blk_begin, const float* __restrict__ ta,
+                                                                int4* __restrict__ hitrows,
+                                                                int32_t* __restrict__ hitrow_count) {
+  constexpr int ROWS = 2 * Z + 1;
+  static_assert(ROWS <= 85, "the trial tag uses bits 21..31 of the third mask word");
+  __shared__ float s_ta[ROWS * 8];
+  __shared__ int4 s_ent[HS_THREADS];
+  __shared__ int s_nent, s_base;
+  hs_load_ta<Z, NH>(ta, s_ta);
+  if (threadIdx.x == 0) s_nent = 0;
   __syncthreads();
-  if (threadIdx.x < cnt) hitrows[s_base + threadIdx.x] = s_ent[threadIdx.x];
+  const int b = blk_begin + (int)blockIdx.x;
+  int lo = 0, hi = ntrials - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (trials[mid].block0 <= b) lo = mid; else hi = mid - 1;
+  }
+  const HsTrial tr = trials[lo];
+  const int groups = (tr.n + 3) / 4;
+  const int lb = b - tr.block0;
+  const int tile = lb < tr.nblocks ? tr.tile_of_block[lb] : -1;
+  const int g = tile * HS_THREADS + threadIdx.x;
+  if (tile >= 0 && g < groups) {
+    const int j0 = 4 * g;
+    unsigned mask[3];
+    hs_phase1_thread<Z, NH>(tr.fop, tr.ld, j0, s_ta, mask);
+    if (mask[0] | mask[1] | mask[2]) {
+      const int pos = atomicAdd(&s_nent, 1);
+      s_ent[pos] = make_int4(j0, (int)mask[0], (int)mask[1], (int)(mask[2] | ((unsigned)lo << 21)));
+    }
+  }
+  __syncthreads();
+  hs_flush_entries(s_ent, s_nent, &s_base, hitrows, hitrow_count);
+}
+
+// Phase 2 for one (entry, row): re-form the row's sums from memory in the
+// same k order as phase 1 (bit-identical) and append its candidates.  Every
+// column index read stays < ld (same bound as phase 1).
+template <int Z, int NH>
+__device__ __forceinline__ void hs_emit_row(const float* __restrict__ fop, int64_t ld, int n, int j0, int r,
+                                            const float* __restrict__ ta, fdas_cand* __restrict__ cands, int cap,
+                                            int32_t* __restrict__ counts) {
+  constexpr int ROWS = 2 * Z + 1;
+  const int i = r - Z;
+  // all loads first (independent), then the sums in k order
+  const float4 v = *reinterpret_cast<const float4*>(fop + (size_t)r * ld + j0);
+  float src[NH + 1][4];
+#pragma unroll
+  for (int m = 2; m <= NH; ++m) {
+    const float* rowp = fop + (size_t)(i / m + Z) * ld;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) src[m][a] = rowp[(j0 + a) / m];
+  }
+  float hk[NH + 1][4];
+  hk[1][0] = v.x;
+  hk[1][1] = v.y;
+  hk[1][2] = v.z;
+  hk[1][3] = v.w;
+#pragma unroll
+  for (int m = 2; m <= NH; ++m)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) hk[m][a] = hk[m - 1][a] + src[m][a];
+  // reserve per plane, then write
+#pragma unroll
+  for (int m = 1; m <= NH; ++m) {
+    const float t = ta[(m - 1) * ROWS + r];
+    int c = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) c += (j0 + a < n && hk[m][a] > t) ? 1 : 0;
+    if (c) {
+      int slot = atomicAdd(&counts[m - 1], c);
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if (j0 + a < n && hk[m][a] > t) {
+          if (slot < cap)
+            *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
+                make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
+          ++slot;
+        }
+      }
+    }
+  }
 }
 
 // Phase 2: work item w = entry * ROWS + row, grid-stride over all items.
@@ -381,48 +498,34 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_emit(const float* __rest
     const int r = (int)(w % ROWS);
     const unsigned word = (unsigned)(r < 32 ? ent.y : (r < 64 ? ent.z : ent.w));
     if (!((word >> (r % 32)) & 1u)) continue;
-    const int j0 = ent.x;
-    const int i = r - Z;
-    // all loads first (independent), then the sums in k order; every column
-    // index read stays < ld (same bound as phase 1)
-    const float4 v = *reinterpret_cast<const float4*>(fop + (size_t)r * ld + j0);
-    float src[NH + 1][4];
-#pragma unroll
-    for (int m = 2; m <= NH; ++m) {
-      const float* rowp = fop + (size_t)(i / m + Z) * ld;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) src[m][a] = rowp[(j0 + a) / m];
-    }
-    float hk[NH + 1][4];
-    hk[1][0] = v.x;
-    hk[1][1] = v.y;
-    hk[1][2] = v.z;
-    hk[1][3] = v.w;
-#pragma unroll
-    for (int m = 2; m <= NH; ++m)
-#pragma unroll
-      for (int a = 0; a < 4; ++a) hk[m][a] = hk[m - 1][a] + src[m][a];
-    // reserve per plane, then write
-#pragma unroll
-    for (int m = 1; m <= NH; ++m) {
-      const float t = ta[(m - 1) * ROWS + r];
-      int c = 0;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) c += (j0 + a < n && hk[m][a] > t) ? 1 : 0;
-      if (c) {
-        int slot = atomicAdd(&counts[m - 1], c);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          if (j0 + a < n && hk[m][a] > t) {
-            if (slot < cap)
-              *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
-                  make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
-            ++slot;
-          }
-        }
-      }
-    }
+    hs_emit_row<Z, NH>(fop, ld, n, ent.x, r, ta, cands, cap, counts);
   }
+}
+
+// Batch form of phase 2: the entry's trial is in bits 21..31 of its third word.
+template <int Z, int NH>
+__global__ __launch_bounds__(HS_THREADS) void k_harmsum_emit_batch(const HsTrial* __restrict__ trials,
+                                                                   const int4* __restrict__ hitrows,
+                                                                   const int32_t* __restrict__ hitrow_count,
+                                                                   const float* __restrict__ ta, int cap) {
+  constexpr int ROWS = 2 * Z + 1;
+  const int64_t items = (int64_t)(*hitrow_count) * ROWS;
+  for (int64_t w = (int64_t)blockIdx.x * HS_THREADS + threadIdx.x; w < items;
+       w += (int64_t)gridDim.x * HS_THREADS) {
+    const int4 ent = hitrows[w / ROWS];
+    const int r = (int)(w % ROWS);
+    const unsigned w2 = (unsigned)ent.w & 0x1FFFFFu;
+    const unsigned word = (unsigned)(r < 32 ? ent.y : (r < 64 ? ent.z : (int)w2));
+    if (!((word >> (r % 32)) & 1u)) continue;
+    const HsTrial& tr = trials[(unsigned)ent.w >> 21];
+    hs_emit_row<Z, NH>(tr.fop, tr.ld, tr.n, ent.x, r, ta, tr.cands, cap, tr.counts);
+  }
+}
+
+// counts[0 .. nh) of every trial of a batch set to 0
+__global__ void k_zero_counts_batch(const HsTrial* __restrict__ trials, int ntrials, int nh) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ntrials * nh) trials[i / nh].counts[i % nh] = 0;
 }
 
 __global__ void k_fill_i32(int32_t* p, int count, int32_t value) {
@@ -437,6 +540,43 @@ int harmsum_tile_columns() { return 4 * HS_THREADS; }
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32, dim3((count + 255) / 256), dim3(256), 0, s, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_counts_batch(const HsTrial* trials, int ntrials, int nh, hipStream_t s) {
+  const int total = ntrials * nh;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_counts_batch, dim3((total + 255) / 256), dim3(256), 0, s, trials, ntrials, nh);
+  return hipGetLastError();
+}
+
+hipError_t launch_harmsum_batch85(const HsTrial* trials, int ntrials, int blk_begin, int blk_end, int n_harm,
+                                  const float* ta, int cap, int4* hitrows, int32_t* hitrow_count, int eblocks,
+                                  hipStream_t s) {
+  if (blk_end <= blk_begin) return hipSuccess;
+  hipError_t e = launch_fill_i32(hitrow_count, 1, 0, s);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)(blk_end - blk_begin);
+  switch (n_harm) {
+#define FDAS_HSB_CASE(NH)                                                                                     \
+  case NH:                                                                                                    \
+    hipLaunchKernelGGL((k_harmsum_z_batch<42, NH>), dim3(blocks), dim3(HS_THREADS), 0, s, trials, ntrials,    \
+                       blk_begin, ta, hitrows, hitrow_count);                                                 \
+    hipLaunchKernelGGL((k_harmsum_emit_batch<42, NH>), dim3(eblocks), dim3(HS_THREADS), 0, s, trials, hitrows, \
+                       hitrow_count, ta, cap);                                                                \
+    break;
+    FDAS_HSB_CASE(1)
+    FDAS_HSB_CASE(2)
+    FDAS_HSB_CASE(3)
+    FDAS_HSB_CASE(4)
+    FDAS_HSB_CASE(5)
+    FDAS_HSB_CASE(6)
+    FDAS_HSB_CASE(7)
+    FDAS_HSB_CASE(8)
+#undef FDAS_HSB_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -476,7 +616,7 @@ hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, in
     hipError_t e = launch_fill_i32(wk.hitrow_count, 1, 0, s);
     if (e != hipSuccess) return e;
     const unsigned blocks = (unsigned)wk.blocks;
-    const unsigned eblocks = 1024;
+    const unsigned eblocks = (unsigned)(wk.emit_blocks > 0 ? wk.emit_blocks : 1024);
     switch (n_harm) {
 #define FDAS_HSZ_CASE(NH)                                                                                          \
   case NH:                                                                                                         \

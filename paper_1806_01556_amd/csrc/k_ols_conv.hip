@@ -182,6 +182,55 @@ __device__ __forceinline__ void ols_template(const float2 (&F)[16], const float2
                                           (int)((tid + 256 * r) * 4), 0, 0);
 }
 
+// One work item: chunk `chunk` of spectrum x (n bins) and templates
+// [z_lo, z_hi): forward FFT once, then per template multiply, inverse FFT and
+// power of the valid outputs into fop (row stride ld).
+__device__ __forceinline__ void ols_item(const float2* __restrict__ x, int64_t n, float* __restrict__ fop,
+                                         int64_t ld, const float2* __restrict__ H, int64_t chunk, int z_lo,
+                                         int z_hi, int V, int P, const float2 (&tw1)[15], const float2 (&tw2)[15],
+                                         float2* __restrict__ buf1, float2* __restrict__ buf2, int tid) {
+  const int64_t base = chunk * V;
+  float2 v[16];
+  const int64_t in0 = base - P + tid;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int64_t idx = in0 + 256 * r;
+    v[r] = (idx >= 0 && idx < n) ? x[idx] : make_float2(0.0f, 0.0f);
+  }
+  fft4096<-1>(v, tw1, tw2, buf1, buf2, tid);
+  float2 F[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) F[r] = v[r];
+
+  // valid outputs of this chunk: s < V and base + s < n
+  const int64_t lim64 = n - base < (int64_t)V ? n - base : (int64_t)V;
+  const uint32_t out_bytes = (uint32_t)lim64 * 4u;
+
+  float2 hA[16], hB[16];
+  {
+    const float2* Hz = H + (size_t)z_lo * kOlsC;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) hA[r] = Hz[tid + 256 * r];
+  }
+  // two templates per trip with ping-pong prefetch buffers (no register copies)
+  for (int z = z_lo; z < z_hi; z += 2) {
+    ols_template(F, hA, hB, z + 1 < z_hi, H + (size_t)(z + 1) * kOlsC, fop + (size_t)z * ld + base, out_bytes,
+                 tw1, tw2, buf1, buf2, tid);
+    if (z + 1 < z_hi)
+      ols_template(F, hB, hA, z + 2 < z_hi, H + (size_t)(z + 2) * kOlsC, fop + (size_t)(z + 1) * ld + base,
+                   out_bytes, tw1, tw2, buf1, buf2, tid);
+  }
+}
+
+__device__ __forceinline__ void load_twiddles(const float2* __restrict__ tw1tab, const float2* __restrict__ tw2tab,
+                                              float2 (&tw1)[15], float2 (&tw2)[15], int tid) {
+#pragma unroll
+  for (int k = 1; k < 16; ++k) {
+    tw1[k - 1] = tw1tab[k * 256 + tid];
+    tw2[k - 1] = tw2tab[k * 16 + (tid & 15)];
+  }
+}
+
 // Persistent grid: work item = (chunk, template group), item = chunk * groups + group,
 // visited with stride gridDim.x.
 __global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x, int64_t n,
@@ -193,68 +242,57 @@ __global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x
   __shared__ float2 buf1[16 * RS];
   __shared__ float2 buf2[16 * RS];
   const int tid = threadIdx.x;
-
   float2 tw1[15], tw2[15];
-#pragma unroll
-  for (int k = 1; k < 16; ++k) {
-    tw1[k - 1] = tw1tab[k * 256 + tid];
-    tw2[k - 1] = tw2tab[k * 16 + (tid & 15)];
-  }
-
+  load_twiddles(tw1tab, tw2tab, tw1, tw2, tid);
   for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
     const int64_t chunk = item / groups;
     const int grp = (int)(item - chunk * groups);
-    const int64_t base = chunk * V;
     const int z_lo = grp * tpg;
-    const int z_hi = min(rows, z_lo + tpg);
+    ols_item(x, n, fop, ld, H, chunk, z_lo, min(rows, z_lo + tpg), V, P, tw1, tw2, buf1, buf2, tid);
+  }
+}
 
-    float2 v[16];
-    const int64_t in0 = base - P + tid;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int64_t idx = in0 + 256 * r;
-      v[r] = (idx >= 0 && idx < n) ? x[idx] : make_float2(0.0f, 0.0f);
+// Batch of spectra: one queue of (trial, chunk, template group) items.  Trial t
+// owns items [trials[t].item0, trials[t+1].item0); this launch works through
+// items [item_begin, item_end) with stride gridDim.x.
+__global__ __launch_bounds__(NT, 2) void k_ols_conv_batch(const ConvTrial* __restrict__ trials, int ntrials,
+                                                          int64_t item_begin, int64_t item_end,
+                                                          const float2* __restrict__ H,
+                                                          const float2* __restrict__ tw1tab,
+                                                          const float2* __restrict__ tw2tab, int rows, int tpg,
+                                                          int groups, int V, int P) {
+  __shared__ float2 buf1[16 * RS];
+  __shared__ float2 buf2[16 * RS];
+  const int tid = threadIdx.x;
+  float2 tw1[15], tw2[15];
+  load_twiddles(tw1tab, tw2tab, tw1, tw2, tid);
+  for (int64_t item = item_begin + blockIdx.x; item < item_end; item += gridDim.x) {
+    // last trial whose first item is <= item (uniform across the workgroup)
+    int lo = 0, hi = ntrials - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (trials[mid].item0 <= item) lo = mid; else hi = mid - 1;
     }
-    fft4096<-1>(v, tw1, tw2, buf1, buf2, tid);
-    float2 F[16];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) F[r] = v[r];
-
-    // valid outputs of this chunk: s < V and base + s < n
-    const int64_t lim64 = n - base < (int64_t)V ? n - base : (int64_t)V;
-    const uint32_t out_bytes = (uint32_t)lim64 * 4u;
-
-    float2 hA[16], hB[16];
-    {
-      const float2* Hz = H + (size_t)z_lo * kOlsC;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) hA[r] = Hz[tid + 256 * r];
-    }
-    // two templates per trip with ping-pong prefetch buffers (no register copies)
-    for (int z = z_lo; z < z_hi; z += 2) {
-      ols_template(F, hA, hB, z + 1 < z_hi, H + (size_t)(z + 1) * kOlsC, fop + (size_t)z * ld + base, out_bytes,
-                   tw1, tw2, buf1, buf2, tid);
-      if (z + 1 < z_hi)
-        ols_template(F, hB, hA, z + 2 < z_hi, H + (size_t)(z + 2) * kOlsC, fop + (size_t)(z + 1) * ld + base,
-                     out_bytes, tw1, tw2, buf1, buf2, tid);
-    }
+    const ConvTrial tr = trials[lo];
+    const int64_t local = item - tr.item0;
+    const int64_t chunk = local / groups;
+    const int grp = (int)(local - chunk * groups);
+    const int z_lo = grp * tpg;
+    ols_item(tr.x, tr.n, tr.fop, tr.ld, H, chunk, z_lo, min(rows, z_lo + tpg), V, P, tw1, tw2, buf1, buf2, tid);
   }
 }
 
 }  // namespace
 
-hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
-                           const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
-                           hipStream_t s) {
-  const int64_t chunks = (n + g.V - 1) / g.V;
-  // Choose the template-group size: every work item pays one forward FFT plus
-  // tpg inverse FFTs, and items run in rounds of `slots` resident workgroups.
+int ols_templates_per_item(int64_t items_per_template, int rows, int slots) {
+  // Every work item pays one forward FFT plus tpg inverse FFTs, and items run
+  // in rounds of `slots` resident workgroups: minimise rounds * (tpg + 1).
   int best_tpg = rows;
   double best = 1e300;
   for (int G = 1; G <= rows; ++G) {
     const int tpg = (rows + G - 1) / G;
     const int groups = (rows + tpg - 1) / tpg;
-    const int64_t items = chunks * groups;
+    const int64_t items = items_per_template * groups;
     const int64_t rounds = (items + slots - 1) / slots;
     const double cost = (double)rounds * (tpg + 1);
     if (cost < best - 1e-9) {
@@ -262,12 +300,30 @@ hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, c
       best_tpg = tpg;
     }
   }
-  const int tpg = best_tpg;
+  return best_tpg;
+}
+
+hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
+                           const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
+                           hipStream_t s) {
+  const int64_t chunks = (n + g.V - 1) / g.V;
+  const int tpg = ols_templates_per_item(chunks, rows, slots);
   const int groups = (rows + tpg - 1) / tpg;
   const int64_t items = chunks * groups;
   const unsigned grid = (unsigned)std::min<int64_t>(items, slots);
   hipLaunchKernelGGL(k_ols_conv, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, tpg, groups, items,
                      g.V, g.P);
+  return hipGetLastError();
+}
+
+hipError_t launch_ols_conv_batch(const ConvTrial* trials, int ntrials, int64_t item_begin, int64_t item_end,
+                                 const float2* H, const float2* tw1, const float2* tw2, int rows, int tpg,
+                                 const OlsGeom& g, int slots, hipStream_t s) {
+  if (item_end <= item_begin) return hipSuccess;
+  const int groups = (rows + tpg - 1) / tpg;
+  const unsigned grid = (unsigned)std::min<int64_t>(item_end - item_begin, slots);
+  hipLaunchKernelGGL(k_ols_conv_batch, dim3(grid), dim3(NT), 0, s, trials, ntrials, item_begin, item_end, H, tw1,
+                     tw2, rows, tpg, groups, g.V, g.P);
   return hipGetLastError();
 }
 

@@ -158,7 +158,20 @@ __global__ __launch_bounds__(ST) void k_sort_scatter(const int4* __restrict__ in
   }
 }
 
+// out[t * nh + k] = ptrs[t][k]: the counts of every trial of a batch in one array
+__global__ void k_gather_counts(int32_t* const* __restrict__ ptrs, int count, int nh, int32_t* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count * nh) out[i] = ptrs[i / nh][i % nh];
+}
+
 }  // namespace
+
+hipError_t launch_gather_counts(int32_t* const* ptrs, int count, int nh, int32_t* out, hipStream_t s) {
+  const int total = count * nh;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_counts, dim3((total + 255) / 256), dim3(256), 0, s, ptrs, count, nh, out);
+  return hipGetLastError();
+}
 
 int sort_tile_count(int m) { return (m + TILE - 1) / TILE; }
 

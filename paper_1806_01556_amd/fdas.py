@@ -29,7 +29,8 @@ HSUM_STRETCH, HSUM_FUNDAMENTAL, HSUM_HIGHEST = 0, 1, 2
 EXPORTED = (
     "fdas_plan_desc_default", "fdas_plan_create", "fdas_plan_destroy", "fdas_convolve",
     "fdas_harmonic_sum", "fdas_candidates", "fdas_last_error", "fdas_abi_version",
-    "fdas_template_taps", "fdas_thresholds",
+    "fdas_template_taps", "fdas_thresholds", "fdas_search_batch", "fdas_candidates_batch",
+    "fdas_autotune", "fdas_set_tuning",
 )
 
 
@@ -52,6 +53,29 @@ class PlanDesc(ctypes.Structure):
 
 class Cand(ctypes.Structure):
     _fields_ = [("harm", ctypes.c_int32), ("z", ctypes.c_int32), ("r", ctypes.c_int32), ("power", ctypes.c_float)]
+
+
+class Trial(ctypes.Structure):
+    _fields_ = [
+        ("d_spectrum", ctypes.c_void_p),
+        ("n", ctypes.c_int64),
+        ("d_fop", ctypes.c_void_p),
+        ("ld", ctypes.c_int64),
+        ("d_cands", ctypes.c_void_p),
+        ("d_counts", ctypes.c_void_p),
+    ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("conv_templates_per_item", ctypes.c_int32),
+        ("conv_workgroups_per_cu", ctypes.c_int32),
+        ("overlap_groups", ctypes.c_int32),
+        ("emit_workgroups", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 CAND_DTYPE = np.dtype([("harm", np.int32), ("z", np.int32), ("r", np.int32), ("power", np.float32)])
@@ -88,8 +112,13 @@ def lib():
     L.fdas_abi_version.restype = i32
     L.fdas_template_taps.argtypes = [i32, vp, i32, ctypes.POINTER(i32)]
     L.fdas_thresholds.argtypes = [i32, dbl, vp]
+    L.fdas_search_batch.argtypes = [vp, ctypes.POINTER(Trial), i32, vp]
+    L.fdas_candidates_batch.argtypes = [vp, ctypes.POINTER(Trial), i32, vp, i64, vp, vp, vp]
+    L.fdas_autotune.argtypes = [vp, ctypes.POINTER(Trial), i32, i32, ctypes.POINTER(Tuning), vp]
+    L.fdas_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     for name in ("fdas_plan_create", "fdas_plan_destroy", "fdas_convolve", "fdas_harmonic_sum",
-                 "fdas_candidates", "fdas_template_taps", "fdas_thresholds"):
+                 "fdas_candidates", "fdas_template_taps", "fdas_thresholds", "fdas_search_batch",
+                 "fdas_candidates_batch", "fdas_autotune", "fdas_set_tuning"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -243,6 +272,57 @@ def thresholds(n_harm=8, p_fa=1e-6):
     out = np.zeros(n_harm, dtype=np.float64)
     _check(lib().fdas_thresholds(int(n_harm), float(p_fa), out.ctypes.data))
     return out
+
+
+# ---- batches of dispersion trials ---------------------------------------------
+
+def trials_array(items):
+    """ctypes array of Trial from (spectrum, n, fop, ld, cands, counts) tuples
+    (torch tensors or integer device addresses)."""
+    arr = (Trial * len(items))()
+    for t, (x, n, fop, ld, cands, counts) in zip(arr, items):
+        t.d_spectrum, t.n, t.d_fop, t.ld = _ptr(x), int(n), _ptr(fop), int(ld)
+        t.d_cands, t.d_counts = _ptr(cands), _ptr(counts)
+    return arr
+
+
+def search_batch(plan, trials, stream=None):
+    """Convolution + harmonic sum of every trial (asynchronous; a Trial array)."""
+    _check(lib().fdas_search_batch(plan.handle, trials, len(trials), _stream(stream)))
+
+
+def candidates_batch(plan, trials, capacity=None, stream=None, allow_overflow=False, copy=True):
+    """Ordered candidates of every trial: (list of CAND_DTYPE arrays, counts[count][n_harm]).
+
+    With copy=False the arrays are views of the plan's page-locked buffer,
+    overwritten by the plan's next readback."""
+    count, nh = len(trials), plan.desc.n_harm
+    if capacity is None:
+        capacity = count * nh * plan.desc.cand_capacity if plan.desc.top_k <= 0 else count * nh * plan.desc.top_k
+    out = _pinned_out(plan, capacity)
+    offs = np.zeros(count + 1, dtype=np.int64)
+    hc = np.zeros((count, nh), dtype=np.int32)
+    st = lib().fdas_candidates_batch(plan.handle, trials, count, out.ctypes.data, int(capacity), offs.ctypes.data,
+                                     hc.ctypes.data, _stream(stream))
+    if not (st == ERR_CAPACITY and allow_overflow):
+        _check(st)
+    views = [out[offs[i]:offs[i + 1]] for i in range(count)]
+    return ([v.copy() for v in views] if copy else views), hc
+
+
+def autotune(plan, trials, repeats=3, stream=None):
+    """Time the batch path over its launch parameters; the fastest is kept in the plan (returned as a dict)."""
+    t = Tuning()
+    _check(lib().fdas_autotune(plan.handle, trials, len(trials), int(repeats), ctypes.byref(t), _stream(stream)))
+    return t.as_dict()
+
+
+def set_tuning(plan, **fields):
+    """Set batch launch parameters by hand (no fields: defaults)."""
+    t = Tuning()
+    for k, v in fields.items():
+        setattr(t, k, int(v))
+    _check(lib().fdas_set_tuning(plan.handle, ctypes.byref(t) if fields else None))
 
 
 # ---- torch conveniences ------------------------------------------------------
