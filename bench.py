@@ -35,6 +35,7 @@ METRIC = "FDAS spectra/s (2^22 pts, 85 templates, 8 harmonics) + % HBM/MFMA roof
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E, published
 FP32_VECTOR_PEAK_TF = 157.3  # MI355X FP32 vector, published
 FP32_MATRIX_PEAK_TF = 157.3  # MI355X FP32 matrix (dense), published
+FP16_MATRIX_PEAK_TF = 2500.0  # MI355X FP16 / BF16 matrix (dense), published
 
 
 def kernel_source_digest(name):
@@ -181,7 +182,7 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--method", choices=("ols", "direct"), default="ols",
+    ap.add_argument("--method", choices=("ols", "direct", "direct-fp16", "direct-bf16"), default="ols",
                     help="FT-convolution method: overlap-save FFT (default, the faster) or the direct "
                          "correlation on the matrix cores")
     ap.add_argument("--pipeline", type=int, default=2,
@@ -217,11 +218,13 @@ def main():
     spec, pulsars = synth.ska(n=n, seed=2)
     x = torch.from_numpy(spec).to(dev)
     method = fdas.CONV_OLS_FFT if args.method == "ols" else fdas.CONV_DIRECT
+    precision = {"direct-fp16": fdas.PREC_SPLIT_FP16, "direct-bf16": fdas.PREC_SPLIT_BF16}.get(args.method,
+                                                                                             fdas.PREC_FP32)
     P = max(1, args.pipeline)
     # P independent plans, FOPs, candidate buffers and streams: step k uses
     # set k % P, so step k's kernels run while step k-1's candidates are
     # ordered and copied back (a plan is used by one stream at a time)
-    plans = [fdas.plan_create(n_max=n, method=method) for _ in range(P)]
+    plans = [fdas.plan_create(n_max=n, method=method, precision=precision) for _ in range(P)]
     fops = [fdas.alloc_fop(plans[i], n, dev) for i in range(P)]
     bufs = [fdas.alloc_cands(plans[i], dev) for i in range(P)]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(P - 1)]
@@ -285,10 +288,17 @@ def main():
     if args.method == "ols":
         conv_flop = 85 * 5 * 4096 * 12 / V * n      # algorithmic FFT flops of one launch
         conv = {"name": "k_ols_conv", "bound": "alu", "peak": FP32_VECTOR_PEAK_TF, "file": "k_ols_conv.hip"}
-    else:
+    elif args.method == "direct":
         taps = sum(2 * (8 + (9 * abs(z) + 1) // 2) for z in range(-42, 43))
         conv_flop = 8 * taps * n                     # one complex multiply-add per template tap and bin
         conv = {"name": "k_direct_conv", "bound": "mfma", "peak": FP32_MATRIX_PEAK_TF,
+                "file": "k_direct_conv.hip"}
+    else:
+        # split precision: three 16-bit products per FP32 product; the
+        # contraction's useful flops counted once, against the 16-bit peak
+        taps = sum(2 * (8 + (9 * abs(z) + 1) // 2) for z in range(-42, 43))
+        conv_flop = 8 * taps * n
+        conv = {"name": "k_direct_conv_split", "bound": "mfma", "peak": FP16_MATRIX_PEAK_TF,
                 "file": "k_direct_conv.hip"}
     kernels = {
         conv["name"]: {"ms": conv_ms, "bound": conv["bound"], "achieved": conv_flop / (conv_ms * 1e-3) / 1e12,
@@ -324,7 +334,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ska_single_spectrum_2^22", "n": n, "templates": 85, "z_max": 42,
                    "harmonics": 8, "p_fa": 1e-6, "pulsars": len(pulsars), "seed": 2,
-                   "method": "ols_fft_c4096" if args.method == "ols" else "direct_mfma_fp32",
+                   "method": {"ols": "ols_fft_c4096", "direct": "direct_mfma_fp32",
+                              "direct-fp16": "direct_mfma_split_fp16",
+                              "direct-bf16": "direct_mfma_split_bf16"}[args.method],
                    "pipeline": P},
         "roofline": roof,
         "stages_ms": {"convolve": round(conv_ms, 4), "harmonic_sum": round(hs_ms, 4),

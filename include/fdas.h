@@ -63,9 +63,15 @@ enum {
   FDAS_CONV_DIRECT = 2    /* direct complex FIR sum on the matrix cores (eq. (1)) */
 };
 
-/* Arithmetic of the direct method (the overlap-save method is always FP32). */
+/* Arithmetic of the direct method (the overlap-save method is always FP32).
+ * The split forms carry every operand value v as hi = round16(v) and
+ * lo = round16(v - hi) and each product as hi*hi + hi*lo + lo*hi on the 16-bit
+ * matrix cores with FP32 accumulation (FP16 operands are scaled by exact
+ * powers of two per workgroup strip and per template tile). */
 enum {
-  FDAS_PREC_FP32 = 0
+  FDAS_PREC_FP32 = 0,
+  FDAS_PREC_SPLIT_FP16 = 1,
+  FDAS_PREC_SPLIT_BF16 = 2
 };
 
 /* Harmonic index map used by fdas_harmonic_sum.  Algorithm 1 names a

@@ -39,6 +39,8 @@ fdas_status hip_fail(hipError_t e, const char* what) {
 void free_plan(fdas_plan* p) {
   if (!p) return;
   if (p->d_Bpk) (void)hipFree(p->d_Bpk);
+  if (p->d_Bsp) (void)hipFree(p->d_Bsp);
+  if (p->d_tscale) (void)hipFree(p->d_tscale);
   if (p->d_dtiles) (void)hipFree(p->d_dtiles);
   if (p->d_drows) (void)hipFree(p->d_drows);
   if (p->d_H) (void)hipFree(p->d_H);
@@ -183,7 +185,11 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   if (desc->top_k < 0) return fail(FDAS_ERR_INVALID_ARG, "top_k < 0");
   if (desc->method != FDAS_CONV_AUTO && desc->method != FDAS_CONV_OLS_FFT && desc->method != FDAS_CONV_DIRECT)
     return fail(FDAS_ERR_INVALID_ARG, "unknown method %d", (int)desc->method);
-  if (desc->precision != FDAS_PREC_FP32) return fail(FDAS_ERR_UNSUPPORTED, "precision %d is not built", (int)desc->precision);
+  if (desc->precision != FDAS_PREC_FP32 && desc->precision != FDAS_PREC_SPLIT_FP16 &&
+      desc->precision != FDAS_PREC_SPLIT_BF16)
+    return fail(FDAS_ERR_INVALID_ARG, "unknown precision %d", (int)desc->precision);
+  if (desc->precision != FDAS_PREC_FP32 && desc->method != FDAS_CONV_DIRECT)
+    return fail(FDAS_ERR_INVALID_ARG, "split precisions apply to the direct method only");
   if (desc->hsum_index != FDAS_HSUM_STRETCH && desc->hsum_index != FDAS_HSUM_FUNDAMENTAL &&
       desc->hsum_index != FDAS_HSUM_HIGHEST)
     return fail(FDAS_ERR_INVALID_ARG, "unknown hsum_index %d", (int)desc->hsum_index);
@@ -220,9 +226,14 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   std::vector<std::vector<std::complex<double>>> bank;
   fdas::template_bank(desc->z_max, bank);
   p->direct = desc->method == FDAS_CONV_DIRECT;
-  std::vector<float> H, tw1, tw2, Bpk;
+  std::vector<float> H, tw1, tw2, Bpk, tscale;
+  std::vector<uint16_t> Bsp;
   std::vector<int> dtiles, drows;
-  if (p->direct) {
+  if (p->direct && desc->precision != FDAS_PREC_FP32) {
+    fdas::direct_pack_split(bank, desc->z_max, desc->precision == FDAS_PREC_SPLIT_BF16, Bsp, tscale, dtiles, drows,
+                            &p->dP_max, &p->dP8_max);
+    p->dtiles = (int)dtiles.size() / 4;
+  } else if (p->direct) {
     fdas::direct_pack(bank, desc->z_max, Bpk, dtiles, drows, &p->dP_max, &p->dP8_max);
     p->dtiles = (int)dtiles.size() / 4;
   } else {
@@ -235,7 +246,15 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
     for (int r = 0; r < p->rows; ++r) p->h_ta[(size_t)(k - 1) * p->rows + r] = t;
   }
 
-  if (p->direct) {
+  if (p->direct && desc->precision != FDAS_PREC_FP32) {
+    if ((e = upload(&p->d_Bsp, Bsp.data(), Bsp.size() * sizeof(uint16_t))) != hipSuccess ||
+        (e = upload(&p->d_tscale, tscale.data(), tscale.size() * sizeof(float))) != hipSuccess ||
+        (e = upload(&p->d_dtiles, dtiles.data(), dtiles.size() * sizeof(int))) != hipSuccess ||
+        (e = upload(&p->d_drows, drows.data(), drows.size() * sizeof(int))) != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "uploading the split direct-method template operand");
+    }
+  } else if (p->direct) {
     if ((e = upload(&p->d_Bpk, Bpk.data(), Bpk.size() * sizeof(float))) != hipSuccess ||
         (e = upload(&p->d_dtiles, dtiles.data(), dtiles.size() * sizeof(int))) != hipSuccess ||
         (e = upload(&p->d_drows, drows.data(), drows.size() * sizeof(int))) != hipSuccess) {
@@ -293,9 +312,14 @@ fdas_status fdas_convolve(fdas_plan* p, const void* d_spectrum, int64_t n, float
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   hipError_t e;
   if (p->direct) {
-    const fdas::DirectTables t{p->d_Bpk, p->d_dtiles, p->d_drows, p->dtiles, p->dP_max, p->dP8_max};
-    e = fdas::launch_direct_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, t,
-                                 static_cast<hipStream_t>(stream));
+    const fdas::DirectTables t{p->d_Bpk, p->d_dtiles, p->d_drows, p->dtiles, p->dP_max, p->dP8_max,
+                               p->d_Bsp, p->d_tscale};
+    if (p->desc.precision == FDAS_PREC_FP32)
+      e = fdas::launch_direct_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, t,
+                                   static_cast<hipStream_t>(stream));
+    else
+      e = fdas::launch_direct_conv_split(static_cast<const float2*>(d_spectrum), n, d_fop, ld, t,
+                                         p->desc.precision == FDAS_PREC_SPLIT_BF16, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "launching the direct correlation");
   } else {
     e = fdas::launch_ols_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2,

@@ -63,6 +63,16 @@ hipError_t launch_ols_conv_batch(const ConvTrial* trials, int ntrials, int64_t i
                                  const float2* H, const float2* tw1, const float2* tw2, int rows, int tpg,
                                  const OlsGeom& g, int slots, hipStream_t s);
 
+// Split 16-bit form of the packed operand: templates ordered and tiled as in
+// direct_pack; tile g covers 2 P8 taps in P8/8 groups of 16, each group 64
+// lanes x 8 hi values then 64 x 8 lo values (16-bit patterns, lane group
+// kg = lane/16 holding taps 4kg..4kg+3 as (Re, Im) pairs).  Tile values are
+// scaled by 2^eh (largest magnitude brought to about 2^14); tscale[g] = 2^-eh.
+// tiles[4g + 1] counts 16-tap groups.  bf16 selects bfloat16, else FP16.
+void direct_pack_split(const std::vector<std::vector<std::complex<double>>>& bank, int z_max, bool bf16,
+                       std::vector<uint16_t>& Bsp, std::vector<float>& tscale, std::vector<int>& tiles,
+                       std::vector<int>& rows, int* P_max, int* P8_max);
+
 struct DirectTables {
   const float* Bpk;    // packed template operand
   const int4* tiles;   // per tile {P, first pair, members, padded pairs}
@@ -70,12 +80,16 @@ struct DirectTables {
   int ntiles;
   int P_max;    // largest P over the tiles
   int P8_max;   // largest padded pair count
+  const uint4* Bsp = nullptr;     // split 16-bit operand (split precisions)
+  const float* tscale = nullptr;  // per-tile 2^-eh (split precisions)
 };
 int direct_block_bins();
 int direct_max_half_taps();
 size_t direct_lds_bytes(int P_max, int P8_max);
 hipError_t launch_direct_conv(const float2* x, int64_t n, float* fop, int64_t ld, const DirectTables& t,
                               hipStream_t s);
+hipError_t launch_direct_conv_split(const float2* x, int64_t n, float* fop, int64_t ld, const DirectTables& t,
+                                    bool bf16, hipStream_t s);
 
 // Columns handled by one workgroup of the 85-row harmonic-sum kernel.
 int harmsum_tile_columns();

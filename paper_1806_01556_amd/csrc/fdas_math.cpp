@@ -220,6 +220,72 @@ void direct_pack(const std::vector<std::vector<cd>>& bank, int z_max, std::vecto
   *P8_max = p8m;
 }
 
+namespace {
+
+// IEEE binary16 and bfloat16 bit patterns, round to nearest even
+uint16_t to_f16_bits(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+float from_f16_bits(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+uint16_t to_bf16_bits(float v) {
+  uint32_t u = __builtin_bit_cast(uint32_t, v);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);  // NaN stays NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+float from_bf16_bits(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
+}  // namespace
+
+void direct_pack_split(const std::vector<std::vector<cd>>& bank, int z_max, bool bf16, std::vector<uint16_t>& Bsp,
+                       std::vector<float>& tscale, std::vector<int>& tiles, std::vector<int>& rows, int* P_max,
+                       int* P8_max) {
+  std::vector<float> Bpk;
+  direct_pack(bank, z_max, Bpk, tiles, rows, P_max, P8_max);  // same order, tiles and supports
+  const int T = (int)tiles.size() / 4;
+  tscale.assign(T, 1.0f);
+  Bsp.clear();
+  int groups = 0;
+  for (int g = 0; g < T; ++g) {
+    const int P = tiles[4 * g + 0], first_pair = tiles[4 * g + 1], P8 = tiles[4 * g + 3];
+    // FP32 value of (tap d, part) for column col, read back from the FP32 pack:
+    // pair p holds taps -P + 2p (k = 0, 1) and -P + 2p + 1 (k = 2, 3)
+    auto val = [&](int d, int part, int col) -> float {
+      const int t = d + P;
+      const int p = t >> 1, k = 2 * (t & 1) + part;
+      if (p >= P8) return 0.0f;
+      return Bpk[((size_t)(first_pair + p)) * 64 + k * 16 + col];
+    };
+    float mx = 0.0f;
+    for (int p = 0; p < P8 * 64; ++p) mx = std::max(mx, std::fabs(Bpk[(size_t)first_pair * 64 + p]));
+    const int eh = mx > 0.0f ? 14 - std::ilogb(mx) : 0;
+    tscale[g] = std::ldexp(1.0f, -eh);
+    tiles[4 * g + 1] = groups;
+    const int G16 = P8 / 8;
+    for (int q = 0; q < G16; ++q) {
+      uint16_t hi[64 * 8], lo[64 * 8];
+      for (int lane = 0; lane < 64; ++lane) {
+        const int col = lane & 15, kg = lane >> 4;
+        for (int e = 0; e < 8; ++e) {
+          const int d = -P + 16 * q + 4 * kg + e / 2;
+          const float v = std::ldexp(val(d, e & 1, col), eh);
+          uint16_t h, l;
+          if (bf16) {
+            h = to_bf16_bits(v);
+            l = to_bf16_bits(v - from_bf16_bits(h));
+          } else {
+            h = to_f16_bits(v);
+            l = to_f16_bits(v - from_f16_bits(h));
+          }
+          hi[lane * 8 + e] = h;
+          lo[lane * 8 + e] = l;
+        }
+      }
+      Bsp.insert(Bsp.end(), hi, hi + 64 * 8);
+      Bsp.insert(Bsp.end(), lo, lo + 64 * 8);
+    }
+    groups += G16;
+  }
+}
+
 void fft_twiddles(std::vector<float>& tw1, std::vector<float>& tw2) {
   // tw1[nb][t] = e^{+2 pi i nb t / 4096} (nb < 16, t < 256); tw2[q][c] = e^{+2 pi i q c / 256}.
   tw1.assign(16 * 256 * 2, 0.0f);

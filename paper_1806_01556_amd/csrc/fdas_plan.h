@@ -20,6 +20,8 @@ struct fdas_plan {
   int4* d_dtiles = nullptr; // direct: per-tile {P, first pair, members, 0}
   int* d_drows = nullptr;   // direct: [tiles][8] FOP rows
   int dtiles = 0, dP_max = 0, dP8_max = 0;
+  uint4* d_Bsp = nullptr;   // direct, split precisions: hi/lo 16-bit operand
+  float* d_tscale = nullptr;  // direct, split precisions: per-tile 2^-eh
   float2* d_H = nullptr;    // [rows][C] template spectra
   float2* d_tw1 = nullptr;  // [16][256]
   float2* d_tw2 = nullptr;  // [16][16]

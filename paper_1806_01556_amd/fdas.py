@@ -22,7 +22,7 @@ STATUS_NAMES = {
     4: "FDAS_ERR_DEVICE", 5: "FDAS_ERR_CAPACITY", 6: "FDAS_ERR_UNSUPPORTED",
 }
 CONV_AUTO, CONV_OLS_FFT, CONV_DIRECT = 0, 1, 2
-PREC_FP32 = 0
+PREC_FP32, PREC_SPLIT_FP16, PREC_SPLIT_BF16 = 0, 1, 2
 HSUM_STRETCH, HSUM_FUNDAMENTAL, HSUM_HIGHEST = 0, 1, 2
 
 #: symbols declared in include/fdas.h
