@@ -221,6 +221,15 @@ fdas_status fdas_autotune(fdas_plan* plan, const fdas_trial* h_trials, int32_t c
 /* Set the launch parameters of the batch path by hand (NULL = defaults). */
 fdas_status fdas_set_tuning(fdas_plan* plan, const fdas_tuning* tuning);
 
+/* As fdas_candidates, but the ordered records land in a page-locked buffer
+ * owned by the plan, written by the device itself, so the call waits once
+ * (no intermediate wait for the counts).  *h_view points at *h_n records in
+ * (harm, z, r) order, valid until the plan's next fdas_candidates_mapped or
+ * fdas_plan_destroy.  h_counts as in fdas_candidates.  With top_k > 0 the
+ * selection runs on the host as in fdas_candidates.  Synchronises. */
+fdas_status fdas_candidates_mapped(fdas_plan* plan, const fdas_cand* d_cands, const int32_t* d_counts,
+                                   const fdas_cand** h_view, int64_t* h_n, int32_t* h_counts, void* stream);
+
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* fdas_last_error(void);
 

@@ -52,6 +52,8 @@ void free_plan(fdas_plan* p) {
   if (p->d_sort_hist) (void)hipFree(p->d_sort_hist);
   if (p->d_sort_totals) (void)hipFree(p->d_sort_totals);
   if (p->h_counts) (void)hipHostFree(p->h_counts);
+  if (p->h_result) (void)hipHostFree(p->h_result);
+  if (p->h_result_counts) (void)hipHostFree(p->h_result_counts);
   for (auto& kv : p->tile_orders) (void)hipFree(kv.second.first);
   if (p->d_hitrows) (void)hipFree(p->d_hitrows);
   if (p->d_hitrow_count) (void)hipFree(p->d_hitrow_count);
@@ -412,6 +414,74 @@ fdas_status fdas_candidates(fdas_plan* p, const fdas_cand* d_cands, const int32_
   if (overflow) return fail(FDAS_ERR_CAPACITY, "a device candidate list overflowed (counts are exact)");
   if (p->desc.top_k <= 0 && nw < total)
     return fail(FDAS_ERR_CAPACITY, "h_capacity %lld < %d candidates", (long long)h_capacity, total);
+  return ok();
+}
+
+fdas_status fdas_candidates_mapped(fdas_plan* p, const fdas_cand* d_cands, const int32_t* d_counts,
+                                   const fdas_cand** h_view, int64_t* h_n, int32_t* h_counts, void* stream) {
+  if (!p) return fail(FDAS_ERR_INVALID_ARG, "plan is NULL");
+  if (!d_cands || !d_counts) return fail(FDAS_ERR_INVALID_ARG, "device candidate buffers are NULL");
+  if (reinterpret_cast<uintptr_t>(d_cands) % 16 != 0)
+    return fail(FDAS_ERR_INVALID_ARG, "candidate buffer must be 16-byte aligned");
+  if (!h_view || !h_n) return fail(FDAS_ERR_INVALID_ARG, "h_view or h_n is NULL");
+  *h_view = nullptr;
+  *h_n = 0;
+  if (p->desc.top_k > 0) {
+    // paper mode selects on the host; serve it through the copying call
+    const int64_t cap = (int64_t)p->desc.n_harm * p->desc.top_k;
+    if (!p->h_result) {
+      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->h_result),
+                                   (size_t)p->desc.n_harm * p->desc.cand_capacity * sizeof(fdas_cand), 0);
+      if (e != hipSuccess) {
+        p->h_result = nullptr;
+        return hip_fail(e, "allocating the page-locked result buffer");
+      }
+    }
+    fdas_status st = fdas_candidates(p, d_cands, d_counts, p->h_result, cap, h_n, h_counts, stream);
+    *h_view = p->h_result;
+    return st;
+  }
+  DeviceGuard dg(p->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int nh = p->desc.n_harm;
+  const int cap = p->desc.cand_capacity;
+  hipError_t e = hipSuccess;
+  if (!p->h_result &&
+      (e = hipHostMalloc(reinterpret_cast<void**>(&p->h_result), (size_t)nh * cap * sizeof(fdas_cand), 0)) != hipSuccess) {
+    p->h_result = nullptr;
+    return hip_fail(e, "allocating the page-locked result buffer");
+  }
+  if (!p->h_result_counts &&
+      (e = hipHostMalloc(reinterpret_cast<void**>(&p->h_result_counts), 8 * sizeof(int32_t), 0)) != hipSuccess) {
+    p->h_result_counts = nullptr;
+    return hip_fail(e, "allocating the page-locked result counts");
+  }
+  void* d_res = nullptr;
+  void* d_rc = nullptr;
+  if ((e = hipHostGetDevicePointer(&d_res, p->h_result, 0)) != hipSuccess ||
+      (e = hipHostGetDevicePointer(&d_rc, p->h_result_counts, 0)) != hipSuccess)
+    return hip_fail(e, "mapping the result buffer");
+  fdas_cand* sorted = nullptr;
+  e = fdas::launch_sort_candidates(d_cands, cap, nh, d_counts, p->rows, p->desc.z_max, p->bits_r, p->d_sort_a,
+                                   p->d_sort_b, p->d_sort_hist, p->d_sort_totals, &sorted, s);
+  if (e == hipSuccess)
+    e = fdas::launch_copy_out(sorted, cap, nh, d_counts, nh * cap, static_cast<fdas_cand*>(d_res),
+                              static_cast<int32_t*>(d_rc), s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "ordering and reading candidates");
+  const int32_t* counts = p->h_result_counts;
+  if (h_counts) std::copy(counts, counts + nh, h_counts);
+  bool overflow = false;
+  int64_t total = 0;
+  for (int k = 0; k < nh; ++k) {
+    if (counts[k] < 0) return fail(FDAS_ERR_DEVICE, "negative candidate count");
+    if (counts[k] > cap) overflow = true;
+    total += std::min(counts[k], cap);
+  }
+  *h_view = p->h_result;
+  *h_n = total;
+  if (overflow) return fail(FDAS_ERR_CAPACITY, "a device candidate list overflowed (counts are exact)");
   return ok();
 }
 

@@ -138,6 +138,11 @@ hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s);
 int sort_tile_count(int m);
 int sort_passes(int rows, int bits_r);
 
+// Ordered records [0, min(total, out_cap)) and the nh counts copied into
+// device-visible page-locked host memory by a kernel.
+hipError_t launch_copy_out(const fdas_cand* sorted, int cap, int nh, const int32_t* counts, int out_cap,
+                           fdas_cand* out, int32_t* counts_out, hipStream_t s);
+
 // out[t * nh + k] = ptrs[t][k] for t < count, k < nh
 hipError_t launch_gather_counts(int32_t* const* ptrs, int count, int nh, int32_t* out, hipStream_t s);
 

@@ -32,6 +32,8 @@ struct fdas_plan {
   int* d_sort_hist = nullptr;     // [256 * tiles] digit histograms
   int* d_sort_totals = nullptr;   // [256 * passes] digit totals per pass
   int32_t* h_counts = nullptr;    // pinned host copy of the device counts
+  fdas_cand* h_result = nullptr;  // page-locked result records of fdas_candidates_mapped
+  int32_t* h_result_counts = nullptr;
   int bits_r = 1;                 // bits of the column index in the sort key
   std::map<int64_t, std::pair<int*, int>> tile_orders;  // n -> (device tile order, workgroups)
   int4* d_hitrows = nullptr;      // [ceil(n_max/4)] rows with hits (harmonic sum phase 1)

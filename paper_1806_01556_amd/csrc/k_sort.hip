@@ -10,13 +10,15 @@
 //                  per-pass digit totals
 //   k_sort_hist    per-tile digit histograms (tile = 1024 records), and the
 //                  digit totals of the pass by atomics
-//   k_sort_scatter each tile forms its own output offsets (exclusive scan of
-//                  the digit totals + the same digit's counts in earlier
-//                  tiles), then scatters stably: ranks within a tile come
-//                  from wave ballots (lanes with equal digits) plus per-wave
-//                  counts
+//   k_sort_offsets one workgroup per digit turns its row of tile counts into
+//                  output offsets (records of smaller digits + the digit's
+//                  records in earlier tiles), in place
+//   k_sort_scatter stable scatter: ranks within a tile come from wave
+//                  ballots (lanes with equal digits) plus per-wave counts
 // Every kernel is launched for the largest possible list (n_harm * capacity
 // records); tiles past the actual count return at once.
+
+#include <algorithm>
 
 #include "fdas_internal.h"
 
@@ -86,34 +88,59 @@ __global__ __launch_bounds__(ST) void k_sort_hist(const int4* __restrict__ in, i
   if (v) atomicAdd(&totals[threadIdx.x], v);
 }
 
+// Output offsets of the pass: for digit d (workgroup d) and tile b,
+// hist[d * maxblk + b] <- (records with a smaller digit) + (records of digit d
+// in tiles before b), computed in place by a workgroup-wide scan of the row.
+__global__ __launch_bounds__(ST) void k_sort_offsets(int* __restrict__ hist, int maxblk,
+                                                     const int* __restrict__ totals, int cap, int nh,
+                                                     const int32_t* __restrict__ counts) {
+  int off[9];
+  const int m = pack_offsets(counts, nh, cap, off);
+  const int nblk = (m + TILE - 1) / TILE;
+  if (nblk == 0) return;
+  __shared__ int sc[ST];
+  __shared__ int s_carry;
+  const int d = blockIdx.x, t = threadIdx.x;
+  // records whose digit is below d
+  sc[t] = t < d ? totals[t] : 0;
+  __syncthreads();
+  for (int o = ST / 2; o > 0; o >>= 1) {
+    if (t < o) sc[t] += sc[t + o];
+    __syncthreads();
+  }
+  if (t == 0) s_carry = sc[0];
+  __syncthreads();
+  int* row = hist + (size_t)d * maxblk;
+  for (int b0 = 0; b0 < nblk; b0 += ST) {
+    const int b = b0 + t;
+    const int v = b < nblk ? row[b] : 0;
+    sc[t] = v;
+    __syncthreads();
+    for (int o = 1; o < ST; o <<= 1) {
+      const int u = t >= o ? sc[t - o] : 0;
+      __syncthreads();
+      sc[t] += u;
+      __syncthreads();
+    }
+    const int carry = s_carry;
+    if (b < nblk) row[b] = carry + sc[t] - v;
+    __syncthreads();
+    if (t == ST - 1) s_carry = carry + sc[t];
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(ST) void k_sort_scatter(const int4* __restrict__ in, int4* __restrict__ out, int cap,
                                                      int nh, const int32_t* __restrict__ counts, int shift,
-                                                     CandKey kp, const int* __restrict__ hist, int maxblk,
-                                                     const int* __restrict__ totals) {
+                                                     CandKey kp, const int* __restrict__ offs, int maxblk) {
   int off[9];
   const int m = pack_offsets(counts, nh, cap, off);
   if ((int)blockIdx.x * TILE >= m) return;  // uniform
   __shared__ int base[256];      // running position per digit inside this tile's output range
-  __shared__ int scan[256];
   __shared__ int wcnt[ST / 64][256];
   const int t = threadIdx.x;
   const int w = t >> 6;
-  {
-    // records of digit t in earlier tiles, and the exclusive scan of the digit totals
-    int before = 0;
-    const int* hp = hist + (size_t)t * maxblk;
-    for (int b = 0; b < (int)blockIdx.x; ++b) before += hp[b];
-    const int tot = totals[t];
-    scan[t] = tot;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-      const int v = t >= o ? scan[t - o] : 0;
-      __syncthreads();
-      scan[t] += v;
-      __syncthreads();
-    }
-    base[t] = scan[t] - tot + before;
-  }
+  base[t] = offs[(size_t)t * maxblk + blockIdx.x];
 #pragma unroll
   for (int q = 0; q < ST / 64; ++q) wcnt[q][t] = 0;
   __syncthreads();
@@ -164,7 +191,27 @@ __global__ void k_gather_counts(int32_t* const* __restrict__ ptrs, int count, in
   if (i < count * nh) out[i] = ptrs[i / nh][i % nh];
 }
 
+// The ordered records and the counts written straight into page-locked host
+// memory (device-visible pointers), so the host waits once: records
+// [0, min(total, out_cap)) of `sorted`, counts[0 .. nh).
+__global__ __launch_bounds__(ST) void k_copy_out(const int4* __restrict__ sorted, int cap, int nh,
+                                                 const int32_t* __restrict__ counts, int out_cap,
+                                                 int4* __restrict__ out, int32_t* __restrict__ counts_out) {
+  int off[9];
+  const int m = min(pack_offsets(counts, nh, cap, off), out_cap);
+  if (blockIdx.x == 0 && (int)threadIdx.x < nh) counts_out[threadIdx.x] = counts[threadIdx.x];
+  for (int i = blockIdx.x * ST + threadIdx.x; i < m; i += gridDim.x * ST) out[i] = sorted[i];
+}
+
 }  // namespace
+
+hipError_t launch_copy_out(const fdas_cand* sorted, int cap, int nh, const int32_t* counts, int out_cap,
+                           fdas_cand* out, int32_t* counts_out, hipStream_t s) {
+  const int blocks = std::max(1, std::min(1024, (nh * cap + ST - 1) / ST));
+  hipLaunchKernelGGL(k_copy_out, dim3(blocks), dim3(ST), 0, s, reinterpret_cast<const int4*>(sorted), cap, nh,
+                     counts, out_cap, reinterpret_cast<int4*>(out), counts_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_gather_counts(int32_t* const* ptrs, int count, int nh, int32_t* out, hipStream_t s) {
   const int total = count * nh;
@@ -195,8 +242,9 @@ hipError_t launch_sort_candidates(const fdas_cand* planes, int cap, int nh, cons
     const int shift = 8 * p;
     int* tot = totals + 256 * p;
     hipLaunchKernelGGL(k_sort_hist, dim3(maxblk), dim3(ST), 0, s, src, cap, nh, counts, shift, kp, hist, maxblk, tot);
+    hipLaunchKernelGGL(k_sort_offsets, dim3(256), dim3(ST), 0, s, hist, maxblk, tot, cap, nh, counts);
     hipLaunchKernelGGL(k_sort_scatter, dim3(maxblk), dim3(ST), 0, s, src, dst, cap, nh, counts, shift, kp, hist,
-                       maxblk, tot);
+                       maxblk);
     int4* tmp = src;
     src = dst;
     dst = tmp;

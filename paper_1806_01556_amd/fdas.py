@@ -30,7 +30,7 @@ EXPORTED = (
     "fdas_plan_desc_default", "fdas_plan_create", "fdas_plan_destroy", "fdas_convolve",
     "fdas_harmonic_sum", "fdas_candidates", "fdas_last_error", "fdas_abi_version",
     "fdas_template_taps", "fdas_thresholds", "fdas_search_batch", "fdas_candidates_batch",
-    "fdas_autotune", "fdas_set_tuning",
+    "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped",
 )
 
 
@@ -116,9 +116,10 @@ def lib():
     L.fdas_candidates_batch.argtypes = [vp, ctypes.POINTER(Trial), i32, vp, i64, vp, vp, vp]
     L.fdas_autotune.argtypes = [vp, ctypes.POINTER(Trial), i32, i32, ctypes.POINTER(Tuning), vp]
     L.fdas_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+    L.fdas_candidates_mapped.argtypes = [vp, vp, vp, ctypes.POINTER(vp), ctypes.POINTER(i64), vp, vp]
     for name in ("fdas_plan_create", "fdas_plan_destroy", "fdas_convolve", "fdas_harmonic_sum",
                  "fdas_candidates", "fdas_template_taps", "fdas_thresholds", "fdas_search_batch",
-                 "fdas_candidates_batch", "fdas_autotune", "fdas_set_tuning"):
+                 "fdas_candidates_batch", "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -241,16 +242,27 @@ def _pinned_out(plan, capacity):
 def candidates(plan, cands, counts, capacity=None, stream=None, allow_overflow=False, copy=True):
     """Ordered candidate records (numpy CAND_DTYPE) and the per-plane device counts.
 
-    The library orders the lists on the device and copies them into a
-    page-locked buffer owned by the plan.  With copy=False the returned array
-    is a view of that buffer, overwritten by the plan's next call.
+    The library orders the lists on the device.  Without a capacity the
+    records are written by the device into a page-locked buffer owned by the
+    plan (fdas_candidates_mapped); with copy=False the returned array is a
+    view of that buffer, overwritten by the plan's next readback.  With a
+    capacity the copying call fdas_candidates is used.
     """
     nh = plan.desc.n_harm
-    if capacity is None:
-        capacity = nh * plan.desc.cand_capacity
-    out = _pinned_out(plan, capacity)
     hc = np.zeros(nh, dtype=np.int32)
     nw = ctypes.c_int64(0)
+    if capacity is None:
+        view = ctypes.c_void_p()
+        st = lib().fdas_candidates_mapped(plan.handle, _ptr(cands), _ptr(counts), ctypes.byref(view),
+                                          ctypes.byref(nw), hc.ctypes.data, _stream(stream))
+        if not (st == ERR_CAPACITY and allow_overflow):
+            _check(st)
+        if nw.value == 0 or not view.value:
+            return np.empty(0, dtype=CAND_DTYPE), hc
+        buf = (ctypes.c_char * (nw.value * CAND_DTYPE.itemsize)).from_address(view.value)
+        res = np.frombuffer(buf, dtype=CAND_DTYPE, count=nw.value)
+        return (res.copy() if copy else res), hc
+    out = _pinned_out(plan, capacity)
     st = lib().fdas_candidates(plan.handle, _ptr(cands), _ptr(counts), out.ctypes.data, int(capacity),
                                ctypes.byref(nw), hc.ctypes.data, _stream(stream))
     if not (st == ERR_CAPACITY and allow_overflow):

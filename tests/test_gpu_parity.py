@@ -266,6 +266,25 @@ def test_candidate_order_large_lists():
     _assert_same_cands(got, ref)
 
 
+@pytest.mark.parametrize("top_k", [0, 50])
+def test_mapped_and_copying_readbacks_agree(top_k):
+    # fdas_candidates_mapped (device writes the page-locked result) and
+    # fdas_candidates (copy into a caller buffer) return the same records,
+    # also after an overflow
+    plan = plan_for(cap=4096, top_k=top_k)
+    rng = np.random.default_rng(12)
+    n = 40000
+    plane = rng.exponential(size=(85, n)).astype(np.float32)
+    for p_fa in (0.02, 0.2):  # the second overflows the 4096-record lists
+        ta = torch.from_numpy(oh.threshold_array(8, 42, p_fa).astype(np.float32)).to(_dev())
+        cands, counts = fdas.alloc_cands(plan, _dev())
+        fdas.harmonic_sum(plan, _upload_plane(plane), n, cands, counts, ta=ta)
+        a, ha = fdas.candidates(plan, cands, counts, allow_overflow=True)
+        b, hb = fdas.candidates(plan, cands, counts, capacity=8 * 4096, allow_overflow=True)
+        assert np.array_equal(ha, hb)
+        _assert_same_cands(a, b)
+
+
 def test_top_k_paper_mode():
     plan = plan_for(top_k=200)
     rng = np.random.default_rng(8)
