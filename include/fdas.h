@@ -230,6 +230,55 @@ fdas_status fdas_set_tuning(fdas_plan* plan, const fdas_tuning* tuning);
 fdas_status fdas_candidates_mapped(fdas_plan* plan, const fdas_cand* d_cands, const int32_t* d_counts,
                                    const fdas_cand** h_view, int64_t* h_n, int32_t* h_counts, void* stream);
 
+/* --- learned block pre-screen -----------------------------------------------
+ * Not part of the paper's method: a small 1D convolutional network over the
+ * zero-drift power of 4096-bin blocks that predicts whether the full search
+ * would find a significant candidate in a block, so that the full search can
+ * run on flagged blocks only (fdas_search_blocks).
+ *   input a0[t] = log(1 + |X[4096 b + t]|^2)  (the template z = 0 is a unit delta,
+ *                 so this is the FOP row z = 0)
+ *   a_l = maxpool4(relu(conv(a_{l-1}))), l = 1..3 (1 -> 32 -> 32 -> 32 channels,
+ *   kernel 9, zero padding 4); h = max_t relu(conv(a_3)); logit = wf.h + bf.
+ *   Loss: weighted logistic, pos_weight * y * softplus(-l) + (1 - y) * softplus(l),
+ *   mean over the batch.  Parameters: FP32 master copy, BF16 copy used by every
+ *   kernel (FP32 accumulation), Adam updates.  Flat parameter order: W1[32][1][9],
+ *   b1, W2[32][32][9], b2, W3, b3, W4, b4, wf[32], bf (fdas_prescreen_param_count). */
+typedef struct fdas_prescreen fdas_prescreen;
+
+int32_t fdas_prescreen_param_count(void);
+/* Workspace for batches of up to max_batch blocks on `device`; parameters start at 0. */
+fdas_status fdas_prescreen_create(int32_t device, int32_t max_batch, fdas_prescreen** out);
+fdas_status fdas_prescreen_destroy(fdas_prescreen* ps);             /* NULL is a no-op */
+/* FP32 parameters from / to host memory (set also clears the Adam state).  Synchronise. */
+fdas_status fdas_prescreen_set_params(fdas_prescreen* ps, const float* h_theta);
+fdas_status fdas_prescreen_get_params(fdas_prescreen* ps, float* h_theta);
+/* d_features[i][t] = log(1 + |X[4096 h_blocks[i] + t]|^2) (0 past n), float[nblocks][4096]. */
+fdas_status fdas_prescreen_features(fdas_prescreen* ps, const void* d_spectrum, int64_t n, const int32_t* h_blocks,
+                                    int32_t nblocks, float* d_features, void* stream);
+/* d_logits[i] for nblocks feature blocks (asynchronous). */
+fdas_status fdas_prescreen_forward(fdas_prescreen* ps, const float* d_features, int32_t nblocks, float* d_logits,
+                                   void* stream);
+/* Logits, mean loss (d_loss[0]) and, if d_grad != NULL, the mean gradient (float[param_count]). */
+fdas_status fdas_prescreen_gradient(fdas_prescreen* ps, const float* d_features, const float* d_labels,
+                                    int32_t nblocks, float pos_weight, float* d_logits, float* d_loss, float* d_grad,
+                                    void* stream);
+/* One Adam step (beta 0.9 / 0.999) with learning rate lr on this batch. */
+fdas_status fdas_prescreen_train_step(fdas_prescreen* ps, const float* d_features, const float* d_labels,
+                                      int32_t nblocks, float pos_weight, float lr, float* d_logits, float* d_loss,
+                                      void* stream);
+
+/* The two-step search restricted to the listed 4096-bin blocks (h_blocks, any
+ * order, duplicates allowed): the convolution runs on the overlap-save chunks
+ * covering the listed blocks and the columns floor(j/k) their harmonic sums
+ * read, the harmonic sum and compaction on the listed blocks' columns only, so
+ * every candidate reported is one fdas_convolve + fdas_harmonic_sum would
+ * report, with the same power.  FOP columns outside those chunks are not
+ * written.  Plans other than overlap-save / 85 rows / stretch search the whole
+ * spectrum.  Asynchronous (the block lists are uploaded synchronously). */
+fdas_status fdas_search_blocks(fdas_plan* plan, const void* d_spectrum, int64_t n, float* d_fop, int64_t ld,
+                               const int32_t* h_blocks, int32_t nblocks, fdas_cand* d_cands, int32_t* d_counts,
+                               void* stream);
+
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* fdas_last_error(void);
 

@@ -20,10 +20,13 @@ FPGA-based Pulsar Search Modules Using OpenCL"):
 * ``harmonic``  -- the harmonic-summing step of Section 2.2 (Algorithm 1):
   stretch planes, cumulative harmonic planes, per-plane thresholds and the
   candidate list.
+* ``prescreen`` -- not from the paper: the small 1D convolutional network of
+  the learned block pre-screen (forward, loss and backward in float64), the
+  reference for the GPU training and inference kernels.
 
 Every function states the passage it follows.  Readings of passages the
 paper leaves open are stated where they are used and collected in the
 design notes of the repository.
 """
 
-from . import response, fop, harmonic  # noqa: F401
+from . import response, fop, harmonic, prescreen  # noqa: F401

@@ -57,6 +57,7 @@ void free_plan(fdas_plan* p) {
   for (auto& kv : p->tile_orders) (void)hipFree(kv.second.first);
   if (p->d_hitrows) (void)hipFree(p->d_hitrows);
   if (p->d_hitrow_count) (void)hipFree(p->d_hitrow_count);
+  if (p->d_lists) (void)hipFree(p->d_lists);
   free_batch(p);
   delete p;
 }

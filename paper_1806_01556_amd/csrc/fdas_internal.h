@@ -45,6 +45,11 @@ hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld,
                            const float2* H, const float2* tw1, const float2* tw2,
                            int rows, const OlsGeom& g, int slots, hipStream_t s);
 
+// Only the listed overlap-save chunks (chunk_list[0 .. nlist), device array).
+hipError_t launch_ols_conv_list(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
+                                const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
+                                const int* chunk_list, int nlist, hipStream_t s);
+
 // Templates sharing one forward FFT, chosen by a cost model for a queue of
 // items_per_template chunks run on `slots` resident workgroups.
 int ols_templates_per_item(int64_t items_per_template, int rows, int slots);
@@ -154,5 +159,27 @@ hipError_t launch_gather_counts(int32_t* const* ptrs, int count, int nh, int32_t
 hipError_t launch_sort_candidates(const fdas_cand* planes, int cap, int nh, const int32_t* counts, int rows,
                                   int z_max, int bits_r, fdas_cand* a, fdas_cand* b, int* hist, int* totals,
                                   fdas_cand** sorted, hipStream_t s);
+
+// ---- learned block pre-screen (k_prescreen.hip) ----------------------------
+struct PsBuffers {
+  float* theta;          // FP32 master parameters
+  float* grad;           // gradient accumulator (mean over the batch)
+  float* m;              // Adam moments
+  float* v;
+  unsigned short* wbf;   // BF16 copy used by the kernels
+  unsigned short* wflip; // [32][32][9] transposed, flipped kernel of one layer
+  float *a1, *a2, *a3, *r4;               // activations [B][32][1024 / 256 / 64 / 64]
+  unsigned char *arg1, *arg2, *arg3;      // max-pool positions
+  float *dz1, *dz2, *dz3, *dz4;           // pre-activation gradients [B][32][4096 / 1024 / 256 / 64]
+};
+int ps_param_count();
+// features of listed 4096-bin blocks: log(1 + |X|^2)
+hipError_t ps_features(const float2* x, int64_t n, const int* blocks, int nb, float* out, hipStream_t s);
+// forward (logits); with labels also the loss (atomically added, mean) and the gradient into pb.grad
+hipError_t ps_forward_backward(const PsBuffers& pb, const float* feats, int nb, const float* labels, float pos_weight,
+                               float* logits, float* loss, hipStream_t s);
+hipError_t ps_adam(const PsBuffers& pb, float lr, float b1, float b2, float c1, float c2, float eps, hipStream_t s);
+hipError_t ps_round(const PsBuffers& pb, hipStream_t s);
+hipError_t ps_zero(float* p, int n, hipStream_t s);
 
 }  // namespace fdas

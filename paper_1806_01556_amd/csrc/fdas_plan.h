@@ -39,6 +39,8 @@ struct fdas_plan {
   int4* d_hitrows = nullptr;      // [ceil(n_max/4)] rows with hits (harmonic sum phase 1)
   int32_t* d_hitrow_count = nullptr;
   fdas_tuning tuning{};           // batch launch parameters (0 = default)
+  int* d_lists = nullptr;         // fdas_search_blocks: chunk list then tile list
+  int64_t list_cap = 0;
 
   // ---- batch path (fdas_batch.cpp) ----
   int batch_cap = 0;                     // trials the tables below hold

@@ -252,6 +252,28 @@ __global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x
   }
 }
 
+// Listed chunks only: item = i * groups + group over chunk_list[0 .. nlist).
+__global__ __launch_bounds__(NT, 2) void k_ols_conv_list(const float2* __restrict__ x, int64_t n,
+                                                         float* __restrict__ fop, int64_t ld,
+                                                         const float2* __restrict__ H,
+                                                         const float2* __restrict__ tw1tab,
+                                                         const float2* __restrict__ tw2tab, int rows, int tpg,
+                                                         int groups, const int* __restrict__ chunk_list, int nlist,
+                                                         int V, int P) {
+  __shared__ float2 buf1[16 * RS];
+  __shared__ float2 buf2[16 * RS];
+  const int tid = threadIdx.x;
+  float2 tw1[15], tw2[15];
+  load_twiddles(tw1tab, tw2tab, tw1, tw2, tid);
+  const int64_t items = (int64_t)nlist * groups;
+  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
+    const int64_t li = item / groups;
+    const int grp = (int)(item - li * groups);
+    const int z_lo = grp * tpg;
+    ols_item(x, n, fop, ld, H, chunk_list[li], z_lo, min(rows, z_lo + tpg), V, P, tw1, tw2, buf1, buf2, tid);
+  }
+}
+
 // Batch of spectra: one queue of (trial, chunk, template group) items.  Trial t
 // owns items [trials[t].item0, trials[t+1].item0); this launch works through
 // items [item_begin, item_end) with stride gridDim.x.
@@ -313,6 +335,19 @@ hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, c
   const unsigned grid = (unsigned)std::min<int64_t>(items, slots);
   hipLaunchKernelGGL(k_ols_conv, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, tpg, groups, items,
                      g.V, g.P);
+  return hipGetLastError();
+}
+
+hipError_t launch_ols_conv_list(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
+                                const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
+                                const int* chunk_list, int nlist, hipStream_t s) {
+  if (nlist <= 0) return hipSuccess;
+  const int tpg = ols_templates_per_item(nlist, rows, slots);
+  const int groups = (rows + tpg - 1) / tpg;
+  const int64_t items = (int64_t)nlist * groups;
+  const unsigned grid = (unsigned)std::min<int64_t>(items, slots);
+  hipLaunchKernelGGL(k_ols_conv_list, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, tpg, groups,
+                     chunk_list, nlist, g.V, g.P);
   return hipGetLastError();
 }
 

@@ -30,7 +30,10 @@ EXPORTED = (
     "fdas_plan_desc_default", "fdas_plan_create", "fdas_plan_destroy", "fdas_convolve",
     "fdas_harmonic_sum", "fdas_candidates", "fdas_last_error", "fdas_abi_version",
     "fdas_template_taps", "fdas_thresholds", "fdas_search_batch", "fdas_candidates_batch",
-    "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped",
+    "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped", "fdas_prescreen_param_count",
+    "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params", "fdas_prescreen_get_params",
+    "fdas_prescreen_features", "fdas_prescreen_forward", "fdas_prescreen_gradient", "fdas_prescreen_train_step",
+    "fdas_search_blocks",
 )
 
 
@@ -117,9 +120,24 @@ def lib():
     L.fdas_autotune.argtypes = [vp, ctypes.POINTER(Trial), i32, i32, ctypes.POINTER(Tuning), vp]
     L.fdas_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
     L.fdas_candidates_mapped.argtypes = [vp, vp, vp, ctypes.POINTER(vp), ctypes.POINTER(i64), vp, vp]
+    flt = ctypes.c_float
+    L.fdas_prescreen_param_count.argtypes = []
+    L.fdas_prescreen_param_count.restype = i32
+    L.fdas_prescreen_create.argtypes = [i32, i32, ctypes.POINTER(vp)]
+    L.fdas_prescreen_destroy.argtypes = [vp]
+    L.fdas_prescreen_set_params.argtypes = [vp, vp]
+    L.fdas_prescreen_get_params.argtypes = [vp, vp]
+    L.fdas_prescreen_features.argtypes = [vp, vp, i64, vp, i32, vp, vp]
+    L.fdas_prescreen_forward.argtypes = [vp, vp, i32, vp, vp]
+    L.fdas_prescreen_gradient.argtypes = [vp, vp, vp, i32, flt, vp, vp, vp, vp]
+    L.fdas_prescreen_train_step.argtypes = [vp, vp, vp, i32, flt, flt, vp, vp, vp]
+    L.fdas_search_blocks.argtypes = [vp, vp, i64, vp, i64, vp, i32, vp, vp, vp]
     for name in ("fdas_plan_create", "fdas_plan_destroy", "fdas_convolve", "fdas_harmonic_sum",
                  "fdas_candidates", "fdas_template_taps", "fdas_thresholds", "fdas_search_batch",
-                 "fdas_candidates_batch", "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped"):
+                 "fdas_candidates_batch", "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped",
+                 "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params",
+                 "fdas_prescreen_get_params", "fdas_prescreen_features", "fdas_prescreen_forward",
+                 "fdas_prescreen_gradient", "fdas_prescreen_train_step", "fdas_search_blocks"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -335,6 +353,92 @@ def set_tuning(plan, **fields):
     for k, v in fields.items():
         setattr(t, k, int(v))
     _check(lib().fdas_set_tuning(plan.handle, ctypes.byref(t) if fields else None))
+
+
+# ---- learned block pre-screen --------------------------------------------------
+
+BLOCK = 4096
+
+
+class Prescreen:
+    """Owns an fdas_prescreen* (network parameters, Adam state, workspace)."""
+
+    def __init__(self, max_batch=256, device=0):
+        h = ctypes.c_void_p()
+        _check(lib().fdas_prescreen_create(int(device), int(max_batch), ctypes.byref(h)))
+        self.handle = h.value
+        self.max_batch = int(max_batch)
+
+    @staticmethod
+    def param_count():
+        return int(lib().fdas_prescreen_param_count())
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().fdas_prescreen_destroy(self.handle))
+            self.handle = None
+
+    def set_params(self, theta):
+        theta = np.ascontiguousarray(theta, dtype=np.float32)
+        assert theta.size == self.param_count()
+        _check(lib().fdas_prescreen_set_params(self.handle, theta.ctypes.data))
+
+    def get_params(self):
+        out = np.zeros(self.param_count(), dtype=np.float32)
+        _check(lib().fdas_prescreen_get_params(self.handle, out.ctypes.data))
+        return out
+
+    def features(self, spectrum, n, blocks, out, stream=None):
+        blocks = np.ascontiguousarray(blocks, dtype=np.int32)
+        _check(lib().fdas_prescreen_features(self.handle, _ptr(spectrum), int(n), blocks.ctypes.data, blocks.size,
+                                             _ptr(out), _stream(stream)))
+
+    def forward(self, feats, nb, logits, stream=None):
+        _check(lib().fdas_prescreen_forward(self.handle, _ptr(feats), int(nb), _ptr(logits), _stream(stream)))
+
+    def gradient(self, feats, labels, nb, pos_weight, logits, loss, grad=None, stream=None):
+        _check(lib().fdas_prescreen_gradient(self.handle, _ptr(feats), _ptr(labels), int(nb), float(pos_weight),
+                                             _ptr(logits), _ptr(loss), _ptr(grad), _stream(stream)))
+
+    def train_step(self, feats, labels, nb, pos_weight, lr, logits, loss, stream=None):
+        _check(lib().fdas_prescreen_train_step(self.handle, _ptr(feats), _ptr(labels), int(nb), float(pos_weight),
+                                               float(lr), _ptr(logits), _ptr(loss), _stream(stream)))
+
+
+def init_prescreen_params(seed=0):
+    """He-uniform convolution weights, small head weights, zero biases (float32)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin in (1, 32, 32, 32):
+        lim = np.sqrt(6.0 / (cin * 9))
+        parts += [rng.uniform(-lim, lim, size=32 * cin * 9), np.zeros(32)]
+    parts += [rng.uniform(-1.0, 1.0, size=32) / np.sqrt(32.0), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def search_blocks(plan, spectrum, n, fop, blocks, cands, counts, ld=None, stream=None):
+    """The two-step search on the listed 4096-bin blocks only (asynchronous)."""
+    if ld is None:
+        ld = fop.shape[1]
+    blocks = np.ascontiguousarray(blocks, dtype=np.int32)
+    _check(lib().fdas_search_blocks(plan.handle, _ptr(spectrum), int(n), _ptr(fop), int(ld), blocks.ctypes.data,
+                                    blocks.size, _ptr(cands), _ptr(counts), _stream(stream)))
+
+
+def harmonic_closure(blocks, n, n_harm=8):
+    """Blocks plus the blocks holding their harmonic multiples m*j, m = 2..n_harm.
+
+    Under the stretch index map a strong signal at column j raises harmonic
+    sums at columns m*j .. m*j + m - 1, so a block flagged for a signal also
+    needs the blocks of its multiples searched."""
+    nblk = (int(n) + BLOCK - 1) // BLOCK
+    out = set(int(b) for b in blocks)
+    for b in list(out):
+        for m in range(2, n_harm + 1):
+            lo, hi = m * b * BLOCK, min(int(n) - 1, m * ((b + 1) * BLOCK - 1) + m - 1)
+            for q in range(lo // BLOCK, min(nblk - 1, hi // BLOCK) + 1):
+                out.add(q)
+    return np.array(sorted(out), dtype=np.int32)
 
 
 # ---- torch conveniences ------------------------------------------------------

@@ -1,0 +1,185 @@
+"""GPU tests of the learned block pre-screen and of the block-restricted search.
+
+* Features: log(1 + |X|^2) of the listed blocks, against NumPy.
+* Forward logits and the mean gradient against the float64 oracle network
+  evaluated with the BF16-rounded parameters the kernels use: the kernels
+  accumulate in FP32, so logits agree to ~1e-5 relative and each gradient
+  tensor to ~1e-4 of its norm (the bounds below leave a factor of ~10).
+* A few Adam steps on a separable toy set lower the loss.
+* fdas_search_blocks: with every block it returns exactly the plain search's
+  candidates; with a subset, exactly the plain candidates in those columns
+  (bit-identical powers), since each searched column's harmonic sum reads
+  convolved columns only.
+"""
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+from oracle import prescreen as ops  # noqa: E402
+from paper_1806_01556_amd import fdas, synth  # noqa: E402
+
+
+def _dev():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch.device("cuda:0")
+
+
+def bf16_round(a):
+    """Round float32 values to bfloat16 (nearest even), returned as float64."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _blocks(nb, seed):
+    rng = np.random.default_rng(seed)
+    P = rng.exponential(size=(nb, 4096))
+    for b in range(0, nb, 2):  # every other block holds a drifting line
+        t0 = rng.integers(100, 3900)
+        P[b, t0:t0 + rng.integers(1, 40)] += rng.uniform(5, 40)
+    return ops.features(P).astype(np.float32), (np.arange(nb) % 2 == 0).astype(np.float32)
+
+
+def _theta(seed):
+    th = fdas.init_prescreen_params(seed)
+    th[-33:-1] *= 4.0  # a livelier head for the checks
+    return th
+
+
+def test_features_match_numpy():
+    ps = fdas.Prescreen(max_batch=8)
+    try:
+        n = 3 * 4096 + 1000
+        spec, _ = synth.make_spectrum(n, 3)
+        x = torch.from_numpy(spec).to(_dev())
+        blocks = np.array([3, 0, 2], dtype=np.int32)
+        out = torch.full((3, 4096), -1.0, device=_dev())
+        ps.features(x, n, blocks, out)
+        torch.cuda.synchronize()
+        p = np.abs(spec.astype(np.complex128)) ** 2
+        ref = np.zeros((3, 4096))
+        for i, b in enumerate(blocks):
+            seg = p[b * 4096:(b + 1) * 4096]
+            ref[i, :seg.size] = np.log1p(seg)
+        np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
+    finally:
+        ps.destroy()
+
+
+def test_forward_and_gradient_match_oracle():
+    nb = 6
+    X, y = _blocks(nb, 5)
+    theta = _theta(1)
+    th_b = bf16_round(theta)  # what the kernels compute with
+    ps = fdas.Prescreen(max_batch=nb)
+    try:
+        ps.set_params(theta)
+        xf = torch.from_numpy(X).to(_dev())
+        yl = torch.from_numpy(y).to(_dev())
+        logits = torch.zeros(nb, device=_dev())
+        loss = torch.zeros(1, device=_dev())
+        grad = torch.zeros(ps.param_count(), device=_dev())
+        ps.gradient(xf, yl, nb, 3.0, logits, loss, grad)
+        torch.cuda.synchronize()
+        ref_logits = np.array([ops.forward(th_b, X[i].astype(np.float64))[0] for i in range(nb)])
+        got = logits.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - ref_logits) <= 1e-4 * (1.0 + np.abs(ref_logits))), (got, ref_logits)
+        ref_loss, ref_grad = ops.batch_loss_grad(th_b, X.astype(np.float64), y, 3.0)
+        assert abs(float(loss.item()) - ref_loss) <= 1e-4 * (1.0 + ref_loss)
+        g = grad.cpu().numpy().astype(np.float64)
+        offs = np.cumsum([0] + [int(np.prod(s)) for s in ops.param_shapes()])
+        for i in range(len(offs) - 1):
+            a, b = g[offs[i]:offs[i + 1]], ref_grad[offs[i]:offs[i + 1]]
+            scale = max(np.linalg.norm(b), 1e-12)
+            assert np.linalg.norm(a - b) <= 1e-3 * scale + 1e-9, (i, np.linalg.norm(a - b), scale)
+        # forward-only call gives the same logits
+        l2 = torch.zeros(nb, device=_dev())
+        ps.forward(xf, nb, l2)
+        torch.cuda.synchronize()
+        assert torch.equal(l2, logits)
+    finally:
+        ps.destroy()
+
+
+def test_training_lowers_the_loss():
+    nb = 64
+    X, y = _blocks(nb, 9)
+    ps = fdas.Prescreen(max_batch=nb)
+    try:
+        ps.set_params(fdas.init_prescreen_params(2))
+        xf = torch.from_numpy(X).to(_dev())
+        yl = torch.from_numpy(y).to(_dev())
+        logits = torch.zeros(nb, device=_dev())
+        loss = torch.zeros(1, device=_dev())
+        losses = []
+        for step in range(60):
+            ps.train_step(xf, yl, nb, 1.0, 2e-3, logits, loss)
+            losses.append(float(loss.item()))
+        print("loss", losses[0], "->", losses[-1], flush=True)
+        assert losses[-1] < 0.5 * losses[0]
+        acc = np.mean((logits.cpu().numpy() > 0) == (y > 0.5))
+        assert acc >= 0.9
+    finally:
+        ps.destroy()
+
+
+_plan = None
+
+
+def plan42():
+    global _plan
+    if _plan is None:
+        _plan = fdas.plan_create(n_max=1 << 20)
+    return _plan
+
+
+def _plain(plan, x, n):
+    fop = torch.full((85, fdas.fop_ld(n)), float("nan"), device=_dev())
+    cands, counts = fdas.alloc_cands(plan, _dev())
+    fdas.convolve(plan, x, fop, n=n)
+    fdas.harmonic_sum(plan, fop, n, cands, counts)
+    c, _ = fdas.candidates(plan, cands, counts)
+    return c
+
+
+def _blocks_search(plan, x, n, blocks):
+    fop = torch.full((85, fdas.fop_ld(n)), float("nan"), device=_dev())
+    cands, counts = fdas.alloc_cands(plan, _dev())
+    print(f"search_blocks n={n} blocks={len(blocks)}", flush=True)
+    fdas.search_blocks(plan, x, n, fop, blocks, cands, counts)
+    c, _ = fdas.candidates(plan, cands, counts)
+    return c
+
+
+def _same(a, b):
+    assert a.size == b.size, (a.size, b.size)
+    for f in ("harm", "z", "r"):
+        assert np.array_equal(a[f], b[f]), f
+    assert np.array_equal(a["power"].view(np.int32), b["power"].view(np.int32))
+
+
+@pytest.mark.parametrize("n", [4096 * 7 + 123, 1 << 18])
+def test_search_blocks_all_equals_plain(n):
+    plan = plan42()
+    spec, _ = synth.make_spectrum(n, 77, n_random=3, r_range=(1000, n * 0.3), snr_range=(10, 20))
+    x = torch.from_numpy(spec).to(_dev())
+    nblk = (n + 4095) // 4096
+    _same(_blocks_search(plan, x, n, np.arange(nblk)), _plain(plan, x, n))
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_search_blocks_subset_is_exact_on_its_columns(seed):
+    plan = plan42()
+    n = 1 << 20
+    spec, _ = synth.make_spectrum(n, 900 + seed, n_random=4, r_range=(2000, 2e5), snr_range=(8, 20))
+    x = torch.from_numpy(spec).to(_dev())
+    rng = np.random.default_rng(seed)
+    blocks = np.unique(np.concatenate([rng.integers(0, 256, 20), [0, 255, 128]])).astype(np.int32)
+    got = _blocks_search(plan, x, n, blocks)
+    ref = _plain(plan, x, n)
+    ref = ref[np.isin(ref["r"] // 4096, blocks)]
+    _same(got, ref)
