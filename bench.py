@@ -176,6 +176,173 @@ def bench_batch(args, torch, fdas, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_prescreen(args, torch, fdas, synth, dev):
+    """Learned block pre-screen: train on the oracle-labelled 2^16-bin spectra of
+    tests/golden/prescreen_labels.txt (regenerated from their seeds), pick the
+    logit threshold on held-out spectra, then search `trials` SKA-sized
+    spectra (2^22 bins, seeds 6e6 + i, 1-3 pulsars) on the flagged blocks and
+    their harmonic multiples, against the plain search of the same spectra.
+    Recall counts the plain search's significant candidates (power above
+    T_k at a per-cell false-alarm probability of 1e-12) that the pre-screened
+    search also reports."""
+    path = os.path.join(ROOT, "tests", "golden", "prescreen_labels.txt")
+    with open(path) as f:
+        lines = f.read().splitlines()
+    recipe = json.loads(next(l for l in lines if l.startswith("# recipe: "))[len("# recipe: "):])
+    rows = [l.split() for l in lines if l and not l.startswith("#")]
+    n_tr = recipe["n"]
+    bpb = n_tr // 4096
+    ps = fdas.Prescreen(max_batch=256)
+    nspec = len(rows)
+    feats = torch.empty((nspec * bpb, 4096), dtype=torch.float32, device=dev)
+    labels = torch.tensor([float(c) for _, bits in rows for c in bits], dtype=torch.float32, device=dev)
+    t_syn = time.perf_counter()
+    for k, (i, _) in enumerate(rows):
+        i = int(i)
+        spec = synth.make_spectrum(n_tr, recipe["seed0"] + i, n_random=i % 4, r_range=tuple(recipe["r_range"]),
+                                   z_range=tuple(recipe["z_range"]), snr_range=tuple(recipe["snr_range"]),
+                                   harm_range=tuple(recipe["harm_range"]))[0]
+        ps.features(torch.from_numpy(spec).to(dev), n_tr, np.arange(bpb), feats[k * bpb:(k + 1) * bpb])
+    torch.cuda.synchronize()
+    t_syn = time.perf_counter() - t_syn
+    n_val = max(1, nspec // 10)
+    tr = np.arange((nspec - n_val) * bpb)
+    va = np.arange((nspec - n_val) * bpb, nspec * bpb)
+    lab_np = labels.cpu().numpy()
+    pos = float(lab_np[tr].sum())
+    pos_weight = (tr.size - pos) / max(pos, 1.0)
+    ps.set_params(fdas.init_prescreen_params(0))
+    rng = np.random.default_rng(0)  # batch order
+    B = 256
+    xb = torch.empty((B, 4096), dtype=torch.float32, device=dev)
+    yb = torch.empty(B, dtype=torch.float32, device=dev)
+    logit_b = torch.empty(B, dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter()
+    steps, lr = 0, 2e-3
+    for ep in range(args.epochs):
+        perm = torch.from_numpy(rng.permutation(tr)).to(dev)
+        for s0 in range(0, tr.size - B + 1, B):
+            idx = perm[s0:s0 + B]
+            torch.index_select(feats, 0, idx, out=xb)
+            torch.index_select(labels, 0, idx, out=yb)
+            ps.train_step(xb, yb, B, pos_weight, lr * (0.5 ** (ep // 5)), logit_b, loss)
+            steps += 1
+    torch.cuda.synchronize()
+    t_tr = time.perf_counter() - t_tr
+    final_loss = float(loss.item())
+
+    def logits_of(fe, nb):
+        out = torch.empty(nb, dtype=torch.float32, device=dev)
+        for s0 in range(0, nb, B):
+            m = min(B, nb - s0)
+            ps.forward(fe[s0:s0 + m], m, out[s0:s0 + m])
+        return out
+
+    lv = logits_of(feats[va[0]:va[-1] + 1], va.size).cpu().numpy()
+    yv = lab_np[va]
+    # threshold: 99 % of the held-out positive blocks flagged, less a margin of 0.5
+    # (a few positives are single noise cells above the labelling threshold,
+    # which no screen can predict and which are not significant candidates)
+    thr = float(np.quantile(lv[yv > 0.5], 0.01) - 0.5) if (yv > 0.5).any() else 0.0
+    val_flag = float(np.mean(lv > thr))
+    val_recall = float(np.mean(lv[yv > 0.5] > thr)) if (yv > 0.5).any() else 1.0
+
+    # ---- test spectra -------------------------------------------------------
+    n = 1 << 22
+    nblk = n // 4096
+    plan = fdas.plan_create(n_max=n)
+    fop = fdas.alloc_fop(plan, n, dev)
+    cands, counts = fdas.alloc_cands(plan, dev)
+    tsig = fdas.thresholds(8, recipe["p_sig"])
+    fe = torch.empty((nblk, 4096), dtype=torch.float32, device=dev)
+
+    def significant(c):
+        keep = c["power"] > tsig[c["harm"] - 1]
+        return set(zip(c["harm"][keep].tolist(), c["z"][keep].tolist(), c["r"][keep].tolist()))
+
+    # operating points: the held-out threshold, then looser screens
+    qs = [("val_p99", thr)] + [(f"val_q{int(100 * q)}", float(np.quantile(lv[yv > 0.5], q)))
+                               for q in (0.05, 0.2, 0.5)]
+    T = args.trials
+    stats = {name: {"ref": 0, "hit": 0, "pref": 0, "phit": 0, "t": 0.0, "flag": [], "search": []}
+             for name, _ in qs}
+    t_plain = 0.0
+    for ti in range(T):
+        spec, pulsars = synth.make_spectrum(n, 6_000_000 + ti, n_random=1 + ti % 3, r_range=(1e4, 2e6))
+        x = torch.from_numpy(spec).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fdas.convolve(plan, x, fop, n=n)
+        fdas.harmonic_sum(plan, fop, n, cands, counts)
+        c_plain, _ = fdas.candidates(plan, cands, counts, allow_overflow=True)
+        t_plain += time.perf_counter() - t0
+        ref = significant(c_plain)
+        for name, th in qs:
+            st = stats[name]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for s0 in range(0, nblk, B):
+                ps.features(x, n, np.arange(s0, min(nblk, s0 + B)), fe[s0:s0 + B])
+            lg = logits_of(fe, nblk).cpu().numpy()
+            flagged = np.nonzero(lg > th)[0]
+            search = fdas.harmonic_closure(flagged, n)
+            fdas.search_blocks(plan, x, n, fop, search, cands, counts)
+            c_pre, _ = fdas.candidates(plan, cands, counts, allow_overflow=True)
+            st["t"] += time.perf_counter() - t0
+            got = significant(c_pre)
+            st["ref"] += len(ref)
+            st["hit"] += len(ref & got)
+            st["flag"].append(flagged.size / nblk)
+            st["search"].append(search.size / nblk)
+            for p in pulsars:
+                b0 = int(p.r) // 4096
+                if any(abs(r // 4096 - b0) <= 1 for _, _, r in ref):
+                    st["pref"] += 1
+                    st["phit"] += int(any(abs(r // 4096 - b0) <= 1 for _, _, r in (ref & got)))
+    points = {}
+    for name, th in qs:
+        st = stats[name]
+        points[name] = {"logit_threshold": round(th, 4), "spectra_per_s": round(T / st["t"], 3),
+                        "speedup_vs_plain": round(t_plain / st["t"], 3),
+                        "recall_significant_cells": round(st["hit"] / max(st["ref"], 1), 5),
+                        "recall_pulsars": round(st["phit"] / max(st["pref"], 1), 5),
+                        "flagged_block_fraction": round(float(np.mean(st["flag"])), 4),
+                        "searched_block_fraction": round(float(np.mean(st["search"])), 4)}
+    head = points["val_q5"]
+    out = {
+        "metric": "FDAS spectra/s with the learned block pre-screen (2^22 pts, 85 templates, 8 harmonics)",
+        "value": head["spectra_per_s"],
+        "unit": "spectra/s",
+        "n_gpus": 1,
+        "steps": T,
+        "warmup": 0,
+        "ms_per_step": round(1e3 / head["spectra_per_s"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 search, bf16 network weights",
+        "data": "synthetic",
+        "config": {"workload": "prescreen_2^22", "test_spectra": T, "train_spectra": nspec - n_val,
+                   "val_spectra": n_val, "train_n": n_tr, "epochs": args.epochs, "train_steps": steps,
+                   "pos_weight": round(pos_weight, 3), "p_label": recipe.get("p_label"), "p_sig": recipe["p_sig"]},
+        "plain_spectra_per_s": round(T / t_plain, 3),
+        "operating_point": "val_q5: flag blocks whose logit exceeds the 5 % quantile of the held-out "
+                           "positive blocks' logits",
+        "significant_cells": stats["val_q5"]["ref"],
+        "pulsars_detected_by_plain": stats["val_q5"]["pref"],
+        "operating_points": points,
+        "val_flagged_fraction": round(val_flag, 4),
+        "val_block_recall": round(val_recall, 4),
+        "train": {"final_batch_loss": round(final_loss, 5), "seconds": round(t_tr, 2),
+                  "synthesis_s": round(t_syn, 1)},
+    }
+    ps.destroy()
+    plan.destroy()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -191,9 +358,11 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="after timing, copy the FOP buffer 3 times (a plain copy of known size, "
                          "so HBM counters can be scaled to bytes)")
-    ap.add_argument("--workload", choices=("ska", "batch"), default="ska",
+    ap.add_argument("--workload", choices=("ska", "batch", "prescreen"), default="ska",
                     help="ska: one 2^22-bin spectrum per step (the headline); batch: 64 dispersion trials of "
-                         "uneven length per step through the batch calls")
+                         "uneven length per step through the batch calls; prescreen: train the learned block "
+                         "pre-screen on oracle-labelled spectra, then search 2^22-bin spectra on flagged blocks")
+    ap.add_argument("--epochs", type=int, default=12, help="prescreen workload: training epochs")
     ap.add_argument("--trials", type=int, default=64, help="batch workload: trials per step")
     args = ap.parse_args()
 
@@ -213,6 +382,8 @@ def main():
     fdas.lib()  # raises if libfdas.so is missing
     if args.workload == "batch":
         return bench_batch(args, torch, fdas, synth, dev)
+    if args.workload == "prescreen":
+        return bench_prescreen(args, torch, fdas, synth, dev)
 
     n = 1 << 22
     spec, pulsars = synth.ska(n=n, seed=2)
