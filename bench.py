@@ -192,7 +192,7 @@ def bench_prescreen(args, torch, fdas, synth, dev):
     rows = [l.split() for l in lines if l and not l.startswith("#")]
     n_tr = recipe["n"]
     bpb = n_tr // 4096
-    ps = fdas.Prescreen(max_batch=256)
+    ps = fdas.Prescreen(max_batch=1024)  # one inference call covers a 2^22-bin spectrum
     nspec = len(rows)
     feats = torch.empty((nspec * bpb, 4096), dtype=torch.float32, device=dev)
     labels = torch.tensor([float(c) for _, bits in rows for c in bits], dtype=torch.float32, device=dev)
@@ -235,8 +235,8 @@ def bench_prescreen(args, torch, fdas, synth, dev):
 
     def logits_of(fe, nb):
         out = torch.empty(nb, dtype=torch.float32, device=dev)
-        for s0 in range(0, nb, B):
-            m = min(B, nb - s0)
+        for s0 in range(0, nb, ps.max_batch):
+            m = min(ps.max_batch, nb - s0)
             ps.forward(fe[s0:s0 + m], m, out[s0:s0 + m])
         return out
 
@@ -283,8 +283,8 @@ def bench_prescreen(args, torch, fdas, synth, dev):
             st = stats[name]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for s0 in range(0, nblk, B):
-                ps.features(x, n, np.arange(s0, min(nblk, s0 + B)), fe[s0:s0 + B])
+            for s0 in range(0, nblk, ps.max_batch):
+                ps.features(x, n, np.arange(s0, min(nblk, s0 + ps.max_batch)), fe[s0:s0 + ps.max_batch])
             lg = logits_of(fe, nblk).cpu().numpy()
             flagged = np.nonzero(lg > th)[0]
             search = fdas.harmonic_closure(flagged, n)

@@ -134,6 +134,84 @@ __global__ __launch_bounds__(256) void k_ps_conv(const float* __restrict__ x, in
   }
 }
 
+// Inference form of a 32 -> 32 channel layer on the matrix cores
+// (v_mfma_f32_16x16x32_bf16): out[o][t] = sum over kappa = 32 k + i of
+// W[o][i][k] x[i][t + k - 4], as a GEMM with M = 32 channels (two 16-row
+// tiles), K = 288 taps x channels (9 steps of 32 channels) and N = positions.
+// The weights are BF16 already; each activation is carried as hi + lo BF16
+// halves, so two products per step keep FP32-level accuracy.  The input tile
+// sits in LDS position-major ([position][channel], hi and lo), so a lane's 8
+// consecutive channels of one position are one 16-byte read.
+typedef float v4fp __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__global__ __launch_bounds__(256) void k_ps_conv_mfma(const float* __restrict__ x, int L,
+                                                      const unsigned short* __restrict__ w,
+                                                      const unsigned short* __restrict__ bias, int pool,
+                                                      float* __restrict__ out) {
+  __shared__ uint4 xhi[(PT + 8) * PC / 8];  // [PT + 8][32] bf16
+  __shared__ uint4 xlo[(PT + 8) * PC / 8];
+  const int b = blockIdx.y;
+  const int t0 = blockIdx.x * PT;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const float* xb = x + (size_t)b * PC * L;
+  unsigned short* sh = reinterpret_cast<unsigned short*>(xhi);
+  unsigned short* sl = reinterpret_cast<unsigned short*>(xlo);
+  for (int e = tid; e < PC * (PT + 8); e += 256) {
+    const int i = e / (PT + 8), u = e % (PT + 8);
+    const int t = t0 + u - 4;
+    const float v = (t >= 0 && t < L) ? xb[(size_t)i * L + t] : 0.0f;
+    const unsigned short h = f_to_bf16(v);
+    sh[u * PC + i] = h;
+    sl[u * PC + i] = f_to_bf16(v - bf16_to_f(h));
+  }
+  // A operands: o-tile ot, step k: lane holds W[16 ot + lane%16][8 (lane/16) + e][k], e < 8
+  v8bf A[2][PK];
+  const int g = lane >> 4, r = lane & 15;
+#pragma unroll
+  for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+    for (int k = 0; k < PK; ++k) {
+      unsigned short a8[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) a8[e] = w[((size_t)(16 * ot + r) * PC + 8 * g + e) * PK + k];
+      A[ot][k] = __builtin_bit_cast(v8bf, *reinterpret_cast<uint4*>(a8));
+    }
+  __syncthreads();
+  const int ntile = min(PT, L - t0) / 16;
+  for (int tt = wv; tt < ntile; tt += 4) {
+    v4fp acc[2] = {v4fp{0.0f, 0.0f, 0.0f, 0.0f}, v4fp{0.0f, 0.0f, 0.0f, 0.0f}};
+#pragma unroll
+    for (int k = 0; k < PK; ++k) {
+      const int u = 16 * tt + r + k;  // LDS row of position t0 + 16 tt + r + k - 4
+      const v8bf bh = __builtin_bit_cast(v8bf, xhi[u * (PC / 8) + g]);
+      const v8bf bl = __builtin_bit_cast(v8bf, xlo[u * (PC / 8) + g]);
+#pragma unroll
+      for (int ot = 0; ot < 2; ++ot) {
+        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ot][k], bh, acc[ot], 0, 0, 0);
+        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ot][k], bl, acc[ot], 0, 0, 0);
+      }
+    }
+    // lane holds channels o = 16 ot + 4 g + v at position t = t0 + 16 tt + r
+    const int t = t0 + 16 * tt + r;
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = 16 * ot + 4 * g + v;
+        float y = fmaxf(acc[ot][v] + bf16_to_f(bias[o]), 0.0f);
+        if (pool == 4) {
+          y = fmaxf(y, __shfl_xor(y, 1));
+          y = fmaxf(y, __shfl_xor(y, 2));
+          if ((r & 3) == 0) out[((size_t)b * PC + o) * (L / 4) + t / 4] = y;
+        } else {
+          out[((size_t)b * PC + o) * L + t] = y;
+        }
+      }
+  }
+}
+
 // wt[i][o][k] = w[o][i][8 - k]: the data gradient as a forward convolution
 __global__ void k_ps_flip(const unsigned short* __restrict__ w, unsigned short* __restrict__ wt, int cin) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -306,16 +384,26 @@ hipError_t ps_forward_backward(const PsBuffers& pb, const float* feats, int nb, 
                                float* logits, float* loss, hipStream_t s) {
   const unsigned short* w = pb.wbf;
   const dim3 blk(256);
-  // forward
+  const bool train = labels != nullptr;
+  // forward; inference runs the 32-channel layers on the matrix cores, training
+  // on the vector units (it also records the max-pool positions)
   hipLaunchKernelGGL((k_ps_conv<1, 0>), dim3(PBLK / PT, nb), blk, 0, s, feats, PBLK, w + ps_off_w(0),
                      w + ps_off_b(0), 4, pb.a1, pb.arg1, nullptr, nullptr);
-  hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1024 / PT, nb), blk, 0, s, pb.a1, 1024, w + ps_off_w(1), w + ps_off_b(1),
-                     4, pb.a2, pb.arg2, nullptr, nullptr);
-  hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1, nb), blk, 0, s, pb.a2, 256, w + ps_off_w(2), w + ps_off_b(2), 4,
-                     pb.a3, pb.arg3, nullptr, nullptr);
-  hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1, nb), blk, 0, s, pb.a3, 64, w + ps_off_w(3), w + ps_off_b(3), 1,
-                     pb.r4, nullptr, nullptr, nullptr);
-  const bool train = labels != nullptr;
+  if (train) {
+    hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1024 / PT, nb), blk, 0, s, pb.a1, 1024, w + ps_off_w(1),
+                       w + ps_off_b(1), 4, pb.a2, pb.arg2, nullptr, nullptr);
+    hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1, nb), blk, 0, s, pb.a2, 256, w + ps_off_w(2), w + ps_off_b(2), 4,
+                       pb.a3, pb.arg3, nullptr, nullptr);
+    hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1, nb), blk, 0, s, pb.a3, 64, w + ps_off_w(3), w + ps_off_b(3), 1,
+                       pb.r4, nullptr, nullptr, nullptr);
+  } else {
+    hipLaunchKernelGGL(k_ps_conv_mfma, dim3(1024 / PT, nb), blk, 0, s, pb.a1, 1024, w + ps_off_w(1), w + ps_off_b(1),
+                       4, pb.a2);
+    hipLaunchKernelGGL(k_ps_conv_mfma, dim3(1, nb), blk, 0, s, pb.a2, 256, w + ps_off_w(2), w + ps_off_b(2), 4,
+                       pb.a3);
+    hipLaunchKernelGGL(k_ps_conv_mfma, dim3(1, nb), blk, 0, s, pb.a3, 64, w + ps_off_w(3), w + ps_off_b(3), 1,
+                       pb.r4);
+  }
   hipLaunchKernelGGL(k_ps_head, dim3(nb), dim3(64), 0, s, pb.r4, w + ps_off_fc(), w + ps_off_fc() + PC, labels,
                      pos_weight, nb, logits, loss, train ? pb.dz4 : nullptr, pb.grad + ps_off_fc());
   if (!train) return hipGetLastError();

@@ -1,7 +1,8 @@
 """GPU tests of the learned block pre-screen and of the block-restricted search.
 
 * Features: log(1 + |X|^2) of the listed blocks, against NumPy.
-* Forward logits and the mean gradient against the float64 oracle network
+* Forward logits (training kernels and the matrix-core inference kernels) and
+  the mean gradient against the float64 oracle network
   evaluated with the BF16-rounded parameters the kernels use: the kernels
   accumulate in FP32, so logits agree to ~1e-5 relative and each gradient
   tensor to ~1e-4 of its norm (the bounds below leave a factor of ~10).
@@ -96,11 +97,13 @@ def test_forward_and_gradient_match_oracle():
             a, b = g[offs[i]:offs[i + 1]], ref_grad[offs[i]:offs[i + 1]]
             scale = max(np.linalg.norm(b), 1e-12)
             assert np.linalg.norm(a - b) <= 1e-3 * scale + 1e-9, (i, np.linalg.norm(a - b), scale)
-        # forward-only call gives the same logits
+        # the inference call (32-channel layers on the matrix cores, activations
+        # as BF16 hi + lo pairs: ~2^-17 relative per activation) agrees too
         l2 = torch.zeros(nb, device=_dev())
         ps.forward(xf, nb, l2)
         torch.cuda.synchronize()
-        assert torch.equal(l2, logits)
+        got2 = l2.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got2 - ref_logits) <= 1e-4 * (1.0 + np.abs(ref_logits))), (got2, ref_logits)
     finally:
         ps.destroy()
 
