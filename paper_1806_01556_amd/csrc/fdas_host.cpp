@@ -351,8 +351,7 @@ fdas_status fdas_harmonic_sum(fdas_plan* p, const float* d_fop, int64_t n, int64
     hipError_t e0 = fdas::tile_order_for(p, n, &d_order, &order_blocks);
     if (e0 != hipSuccess) return hip_fail(e0, "uploading the harmonic-sum tile order");
   }
-  hipError_t e = fdas::launch_fill_i32(d_counts, p->desc.n_harm, 0, s);
-  if (e != hipSuccess) return hip_fail(e, "clearing the candidate counts");
+  hipError_t e;
   fdas::HsWork wk{d_order, order_blocks, p->d_hitrows, p->d_hitrow_count, p->tuning.emit_workgroups};
   e = fdas::launch_harmsum(d_fop, n, ld, p->desc.z_max, p->desc.n_harm, d_ta ? d_ta : p->d_ta, d_cands,
                            p->desc.cand_capacity, d_counts, wk, p->desc.hsum_index, s);

@@ -133,7 +133,8 @@ hipError_t launch_harmsum_batch85(const HsTrial* trials, int ntrials, int blk_be
                                   const float* ta, int cap, int4* hitrows, int32_t* hitrow_count, int eblocks,
                                   hipStream_t s);
 
-// index: FDAS_HSUM_* (the stretch map uses the two-phase kernels for 85 rows)
+// index: FDAS_HSUM_* (the stretch map uses the two-phase kernels for 85 rows).
+// counts[0 .. n_harm) are reset by the launch.
 hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, int n_harm,
                           const float* ta, fdas_cand* cands, int cap, int32_t* counts,
                           const HsWork& wk, int index, hipStream_t s);

@@ -279,7 +279,7 @@ fdas_status fdas_search_blocks(fdas_plan* p, const void* d_spectrum, int64_t n, 
       ((e = hipStreamSynchronize(s)) != hipSuccess ||
        (e = hipMemcpy(p->d_lists, lists.data(), lists.size() * sizeof(int), hipMemcpyHostToDevice)) != hipSuccess))
     return hip_fail(e, "uploading the block lists");
-  e = launch_fill_i32(d_counts, nh, 0, s);
+  if (tiles.empty()) e = launch_fill_i32(d_counts, nh, 0, s);  // else the harmonic sum resets them
   if (e == hipSuccess && !chunks.empty())
     e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2,
                              p->rows, p->geom, p->conv_slots, p->d_lists, (int)chunks.size(), s);

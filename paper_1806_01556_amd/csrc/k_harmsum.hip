@@ -482,7 +482,10 @@ __device__ __forceinline__ void hs_emit_row(const float* __restrict__ fop, int64
   }
 }
 
-// Phase 2: work item w = entry * ROWS + row, grid-stride over all items.
+// Phase 2: work item w = entry * ROWS + row, grid-stride over all items in
+// wave-uniform steps so the whole wave reaches the compaction together: each
+// plane's slots are reserved with one atomic per wave (lane offsets from
+// ballots of the 3-bit per-lane counts), not one per lane.
 template <int Z, int NH>
 __global__ __launch_bounds__(HS_THREADS) void k_harmsum_emit(const float* __restrict__ fop, int64_t ld, int n,
                                                              const int4* __restrict__ hitrows,
@@ -492,14 +495,80 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_emit(const float* __rest
                                                              int32_t* __restrict__ counts) {
   constexpr int ROWS = 2 * Z + 1;
   const int64_t items = (int64_t)(*hitrow_count) * ROWS;
-  for (int64_t w = (int64_t)blockIdx.x * HS_THREADS + threadIdx.x; w < items;
-       w += (int64_t)gridDim.x * HS_THREADS) {
-    const int4 ent = hitrows[w / ROWS];
-    const int r = (int)(w % ROWS);
-    const unsigned word = (unsigned)(r < 32 ? ent.y : (r < 64 ? ent.z : ent.w));
-    if (!((word >> (r % 32)) & 1u)) continue;
-    hs_emit_row<Z, NH>(fop, ld, n, ent.x, r, ta, cands, cap, counts);
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * HS_THREADS;
+  for (int64_t w0 = (int64_t)blockIdx.x * HS_THREADS + (threadIdx.x & ~63); w0 < items; w0 += stride) {
+    const int64_t w = w0 + lane;
+    bool act = w < items;
+    int4 ent = make_int4(0, 0, 0, 0);
+    int r = 0;
+    if (act) {
+      ent = hitrows[w / ROWS];
+      r = (int)(w % ROWS);
+      const unsigned word = (unsigned)(r < 32 ? ent.y : (r < 64 ? ent.z : ent.w));
+      act = ((word >> (r % 32)) & 1u) != 0;
+    }
+    if (__ballot(act) == 0ull) continue;  // uniform
+    const int j0 = ent.x;
+    const int i = r - Z;
+    float hk[NH + 1][4];
+    if (act) {
+      const float4 v = *reinterpret_cast<const float4*>(fop + (size_t)r * ld + j0);
+      float src[NH + 1][4];
+#pragma unroll
+      for (int m = 2; m <= NH; ++m) {
+        const float* rowp = fop + (size_t)(i / m + Z) * ld;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) src[m][a] = rowp[(j0 + a) / m];
+      }
+      hk[1][0] = v.x;
+      hk[1][1] = v.y;
+      hk[1][2] = v.z;
+      hk[1][3] = v.w;
+#pragma unroll
+      for (int m = 2; m <= NH; ++m)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) hk[m][a] = hk[m - 1][a] + src[m][a];
+    }
+#pragma unroll
+    for (int m = 1; m <= NH; ++m) {
+      int c = 0;
+      float t = 0.0f;
+      if (act) {
+        t = ta[(m - 1) * ROWS + r];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) c += (j0 + a < n && hk[m][a] > t) ? 1 : 0;
+      }
+      const unsigned long long b0 = __ballot(c & 1), b1 = __ballot(c & 2), b2 = __ballot(c & 4);
+      const int total = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+      if (total == 0) continue;  // uniform
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&counts[m - 1], total);
+      base = __shfl(base, 0);
+      auto below = [&](unsigned long long b) {
+        return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+      };
+      int slot = base + below(b0) + 2 * below(b1) + 4 * below(b2);
+      if (c) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (j0 + a < n && hk[m][a] > t) {
+            if (slot < cap)
+              *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
+                  make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
+            ++slot;
+          }
+        }
+      }
+    }
   }
+}
+
+// counts[0 .. nh) = 0 and *extra = 0 in one launch
+__global__ void k_fill_counts(int32_t* __restrict__ counts, int nh, int32_t* __restrict__ extra) {
+  const int t = threadIdx.x;
+  if (t < nh) counts[t] = 0;
+  if (extra && t == 63) *extra = 0;
 }
 
 // Batch form of phase 2: the entry's trial is in bits 21..31 of its third word.
@@ -582,6 +651,13 @@ hipError_t launch_harmsum_batch85(const HsTrial* trials, int ntrials, int blk_be
 
 hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, int n_harm, const float* ta,
                           fdas_cand* cands, int cap, int32_t* counts, const HsWork& wk, int index, hipStream_t s) {
+  // the counts (and the fast path's hit-row counter) start at zero, in one launch
+  const bool fast = z_max == 42 && index == FDAS_HSUM_STRETCH;
+  hipLaunchKernelGGL(k_fill_counts, dim3(1), dim3(64), 0, s, counts, n_harm, fast ? wk.hitrow_count : nullptr);
+  {
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+  }
   if (index == FDAS_HSUM_FUNDAMENTAL || index == FDAS_HSUM_HIGHEST) {
     const int64_t groups = (n + 3) / 4;
     const unsigned blocks = (unsigned)((groups + HS_THREADS - 1) / HS_THREADS);
@@ -613,8 +689,6 @@ hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, in
   const int nn = (int)n;
   if (z_max == 42) {
     // two-phase fast path for the 85-template plane
-    hipError_t e = launch_fill_i32(wk.hitrow_count, 1, 0, s);
-    if (e != hipSuccess) return e;
     const unsigned blocks = (unsigned)wk.blocks;
     const unsigned eblocks = (unsigned)(wk.emit_blocks > 0 ? wk.emit_blocks : 1024);
     switch (n_harm) {
