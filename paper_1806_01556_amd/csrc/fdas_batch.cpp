@@ -40,6 +40,11 @@ void free_batch(fdas_plan* p) {
   if (p->d_cand_ptrs) (void)hipFree(p->d_cand_ptrs);
   if (p->d_counts_all) (void)hipFree(p->d_counts_all);
   if (p->h_counts_all) (void)hipHostFree(p->h_counts_all);
+  if (p->d_rb_tab) (void)hipFree(p->d_rb_tab);
+  if (p->d_bsort_a) (void)hipFree(p->d_bsort_a);
+  if (p->d_bsort_b) (void)hipFree(p->d_bsort_b);
+  if (p->d_bsort_hist) (void)hipFree(p->d_bsort_hist);
+  if (p->d_bsort_totals) (void)hipFree(p->d_bsort_totals);
 }
 
 }  // namespace fdas
@@ -340,50 +345,95 @@ fdas_status fdas_candidates_batch(fdas_plan* p, const fdas_trial* h_trials, int3
     return hip_fail(e, "reading the batch candidate counts");
   if (h_counts) std::memcpy(h_counts, p->h_counts_all, (size_t)count * nh * sizeof(int32_t));
   bool overflow = false;
-  std::vector<int> totals(count);
+  // record i of trial t lands at pre[t] + i of one trial-major array
+  std::vector<int64_t> pre(count + 1, 0);
   for (int i = 0; i < count; ++i) {
-    int tot = 0;
+    int64_t tot = 0;
     for (int k = 0; k < nh; ++k) {
       const int c = p->h_counts_all[i * nh + k];
       if (c < 0) return fail(FDAS_ERR_DEVICE, "negative candidate count");
       if (c > cap) overflow = true;
       tot += std::min(c, cap);
     }
-    totals[i] = tot;
+    pre[i + 1] = pre[i] + tot;
   }
-  int64_t pos = 0;
-  std::vector<fdas_cand> tmp, keep;
-  for (int i = 0; i < count; ++i) {
-    h_offsets[i] = pos;
-    if (totals[i] == 0) continue;
-    fdas_cand* sorted = nullptr;
-    e = launch_sort_candidates(h_trials[i].d_cands, cap, nh, h_trials[i].d_counts, p->rows, p->desc.z_max, p->bits_r,
-                               p->d_sort_a, p->d_sort_b, p->d_sort_hist, p->d_sort_totals, &sorted, s);
+  const int64_t M = pre[count];
+  if (M > INT32_MAX / 2) return fail(FDAS_ERR_CAPACITY, "%lld candidates in one batch readback", (long long)M);
+  if (sort_passes_batch(count, p->rows, p->bits_r) > 8)
+    return fail(FDAS_ERR_INVALID_ARG, "batch sort key of %d trials does not fit 64 bits", count);
+  fdas_cand* sorted = nullptr;
+  if (M > 0) {
+    // buffers: the per-trial table and sort space for M records (grown on demand)
+    if (count > p->rb_tab_cap) {
+      if (p->d_rb_tab) (void)hipFree(p->d_rb_tab);
+      p->d_rb_tab = nullptr;
+      p->rb_tab_cap = 0;
+      if ((e = hipMalloc(reinterpret_cast<void**>(&p->d_rb_tab), (size_t)count * sizeof(RbTrial))) != hipSuccess)
+        return hip_fail(e, "allocating the readback table");
+      p->rb_tab_cap = count;
+    }
+    if (M > p->rb_sort_cap) {
+      if (p->d_bsort_a) (void)hipFree(p->d_bsort_a);
+      if (p->d_bsort_b) (void)hipFree(p->d_bsort_b);
+      if (p->d_bsort_hist) (void)hipFree(p->d_bsort_hist);
+      if (p->d_bsort_totals) (void)hipFree(p->d_bsort_totals);
+      p->d_bsort_a = p->d_bsort_b = nullptr;
+      p->d_bsort_hist = p->d_bsort_totals = nullptr;
+      p->rb_sort_cap = 0;
+      const int64_t want = std::max<int64_t>(M + M / 4, 1 << 16);
+      if ((e = hipMalloc(reinterpret_cast<void**>(&p->d_bsort_a), (size_t)want * sizeof(fdas_cand))) != hipSuccess ||
+          (e = hipMalloc(reinterpret_cast<void**>(&p->d_bsort_b), (size_t)want * sizeof(fdas_cand))) != hipSuccess ||
+          (e = hipMalloc(reinterpret_cast<void**>(&p->d_bsort_hist),
+                         (size_t)256 * sort_tile_count((int)want) * sizeof(int))) != hipSuccess ||
+          (e = hipMalloc(reinterpret_cast<void**>(&p->d_bsort_totals), (size_t)256 * 8 * sizeof(int))) != hipSuccess)
+        return hip_fail(e, "allocating the batch sort buffers");
+      p->rb_sort_cap = want;
+    }
+    e = ensure_tables(p, 1, (size_t)count * sizeof(RbTrial));
+    if (e != hipSuccess) return hip_fail(e, "allocating the batch staging area");
+    RbTrial* tab = static_cast<RbTrial*>(p->h_stage);
+    for (int i = 0; i < count; ++i)
+      tab[i] = RbTrial{reinterpret_cast<const int4*>(h_trials[i].d_cands), h_trials[i].d_counts, pre[i], 0};
+    if ((e = hipMemcpyAsync(p->d_rb_tab, tab, (size_t)count * sizeof(RbTrial), hipMemcpyHostToDevice, s)) !=
+            hipSuccess ||
+        (e = hipEventRecord(p->stage_done, s)) != hipSuccess)
+      return hip_fail(e, "uploading the readback table");
+    e = launch_sort_batch(p->d_rb_tab, count, cap, nh, (int)M, p->rows, p->desc.z_max, p->bits_r, p->d_bsort_a,
+                          p->d_bsort_b, p->d_bsort_hist, p->d_bsort_totals, &sorted, s);
     if (e != hipSuccess) return hip_fail(e, "ordering candidates");
-    if (p->desc.top_k <= 0) {
-      const int64_t nw = std::min<int64_t>(totals[i], h_capacity - pos);
-      if (nw > 0) e = hipMemcpyAsync(h_out + pos, sorted, (size_t)nw * sizeof(fdas_cand), hipMemcpyDeviceToHost, s);
-      if (e != hipSuccess) return hip_fail(e, "reading candidates");
-      if (nw < totals[i]) overflow = true;
-      pos += std::max<int64_t>(nw, 0);
-    } else {
-      tmp.resize(totals[i]);
-      e = hipMemcpyAsync(tmp.data(), sorted, (size_t)totals[i] * sizeof(fdas_cand), hipMemcpyDeviceToHost, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) return hip_fail(e, "reading candidates");
+  }
+  if (p->desc.top_k <= 0) {
+    // one copy of the trial-major array; a short host buffer truncates the last trials
+    const int64_t nw = std::min<int64_t>(M, h_capacity);
+    for (int i = 0; i <= count; ++i) h_offsets[i] = std::min<int64_t>(pre[i], h_capacity);
+    if (nw < M) overflow = true;
+    if (nw > 0 && (e = hipMemcpyAsync(h_out, sorted, (size_t)nw * sizeof(fdas_cand), hipMemcpyDeviceToHost, s)) !=
+                      hipSuccess)
+      return hip_fail(e, "reading candidates");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading candidates");
+  } else {
+    std::vector<fdas_cand> all((size_t)M), keep;
+    if (M > 0 && (e = hipMemcpyAsync(all.data(), sorted, (size_t)M * sizeof(fdas_cand), hipMemcpyDeviceToHost, s)) !=
+                     hipSuccess)
+      return hip_fail(e, "reading candidates");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "reading candidates");
+    int64_t pos = 0;
+    for (int i = 0; i < count; ++i) {
+      h_offsets[i] = pos;
+      if (pre[i + 1] == pre[i]) continue;
       int off[9] = {0};
       for (int k = 0; k < nh; ++k) off[k + 1] = off[k] + std::min(p->h_counts_all[i * nh + k], cap);
       keep.clear();
-      keep_top_k(tmp.data(), off, nh, p->desc.top_k, keep);
+      keep_top_k(all.data() + pre[i], off, nh, p->desc.top_k, keep);
       const int64_t nw = std::min<int64_t>((int64_t)keep.size(), h_capacity - pos);
       if (nw > 0) std::memcpy(h_out + pos, keep.data(), (size_t)nw * sizeof(fdas_cand));
       if (nw < (int64_t)keep.size()) overflow = true;
       pos += std::max<int64_t>(nw, 0);
     }
+    h_offsets[count] = pos;
   }
-  h_offsets[count] = pos;
-  e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(e, "reading candidates");
   if (overflow) return fail(FDAS_ERR_CAPACITY, "a candidate list overflowed (device capacity or h_capacity)");
   return ok();
 }

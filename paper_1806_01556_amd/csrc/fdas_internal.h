@@ -161,6 +161,24 @@ hipError_t launch_sort_candidates(const fdas_cand* planes, int cap, int nh, cons
                                   int z_max, int bits_r, fdas_cand* a, fdas_cand* b, int* hist, int* totals,
                                   fdas_cand** sorted, hipStream_t s);
 
+// One trial of a batch readback: its per-plane lists and device counts, and
+// the index of its first record in the packed array (host prefix of the
+// clamped counts).
+struct RbTrial {
+  const int4* cands;
+  const int32_t* counts;
+  int64_t off;
+  int64_t pad;
+};
+
+int sort_passes_batch(int count, int rows, int bits_r);
+
+// Order the lists of `count` trials (m records in all) as one trial-major
+// array in (trial, harm, z, r) order.  a, b hold m records, hist
+// 256 * sort_tile_count(m) ints, totals 256 * sort_passes_batch ints.
+hipError_t launch_sort_batch(const RbTrial* tab, int count, int cap, int nh, int m, int rows, int z_max, int bits_r,
+                             fdas_cand* a, fdas_cand* b, int* hist, int* totals, fdas_cand** sorted, hipStream_t s);
+
 // ---- learned block pre-screen (k_prescreen.hip) ----------------------------
 struct PsBuffers {
   float* theta;          // FP32 master parameters

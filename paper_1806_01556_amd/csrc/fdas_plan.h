@@ -56,6 +56,13 @@ struct fdas_plan {
   int32_t* d_counts_all = nullptr;       // candidates_batch: gathered counts [cap][n_harm]
   int32_t* h_counts_all = nullptr;       // pinned copy
   int counts_cap = 0;
+  fdas::RbTrial* d_rb_tab = nullptr;     // candidates_batch: per-trial readback table
+  int rb_tab_cap = 0;
+  fdas_cand* d_bsort_a = nullptr;        // candidates_batch: sort buffers of rb_sort_cap records
+  fdas_cand* d_bsort_b = nullptr;
+  int* d_bsort_hist = nullptr;           // [256 * tiles]
+  int* d_bsort_totals = nullptr;         // [256 * 8]
+  int64_t rb_sort_cap = 0;
   hipStream_t cap_stream = nullptr;      // stream the batch graph is recorded on
   hipStream_t side_stream = nullptr;     // harmonic sums overlapping later convolutions
   std::vector<hipEvent_t> fork_events;   // one per overlap group, plus the join

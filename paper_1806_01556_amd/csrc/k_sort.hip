@@ -17,6 +17,13 @@
 //                  ballots (lanes with equal digits) plus per-wave counts
 // Every kernel is launched for the largest possible list (n_harm * capacity
 // records); tiles past the actual count return at once.
+//
+// A batch of trials is ordered as one array (k_sort_pack_batch): while they
+// are sorted, records carry their trial number in bits 8 and up of the
+// harmonic field and the key puts the trial above the plane slot, so the
+// sorted array is trial-major with every trial's records in its own canonical
+// order; the last scatter pass clears the tag.  The batch record count is
+// known to the host, so those launches are sized exactly.
 
 #include <algorithm>
 
@@ -31,10 +38,13 @@ constexpr int TILE = ST * SPT;     // 1024 records per tile
 
 struct CandKey {
   int rows, z_max, bits_r;
+  int batch;  // records carry their trial in bits 8.. of the harmonic field
 };
 
 __device__ __forceinline__ unsigned long long cand_key(const int4 c, const CandKey kp) {
-  const unsigned long long slot = (unsigned long long)((c.x - 1) * kp.rows + (c.y + kp.z_max));
+  const int harm = kp.batch ? (c.x & 255) : c.x;
+  unsigned long long slot = (unsigned long long)((harm - 1) * kp.rows + (c.y + kp.z_max));
+  if (kp.batch) slot += (unsigned long long)((unsigned)c.x >> 8) * 8ull * (unsigned long long)kp.rows;
   return (slot << kp.bits_r) | (unsigned long long)(unsigned)c.z;
 }
 
@@ -48,6 +58,13 @@ __device__ __forceinline__ int pack_offsets(const int32_t* __restrict__ counts, 
     off[k + 1] = off[k] + c;
   }
   return off[8];
+}
+
+// records of the list: m_fixed when the host knows it (batch), else from the counts
+__device__ __forceinline__ int record_count(const int32_t* __restrict__ counts, int nh, int cap, int m_fixed) {
+  if (m_fixed >= 0) return m_fixed;
+  int off[9];
+  return pack_offsets(counts, nh, cap, off);
 }
 
 __global__ __launch_bounds__(ST) void k_sort_pack(const int4* __restrict__ planes, int cap, int nh,
@@ -65,10 +82,10 @@ __global__ __launch_bounds__(ST) void k_sort_pack(const int4* __restrict__ plane
 }
 
 __global__ __launch_bounds__(ST) void k_sort_hist(const int4* __restrict__ in, int cap, int nh,
-                                                  const int32_t* __restrict__ counts, int shift, CandKey kp,
-                                                  int* __restrict__ hist, int maxblk, int* __restrict__ totals) {
-  int off[9];
-  const int m = pack_offsets(counts, nh, cap, off);
+                                                  const int32_t* __restrict__ counts, int m_fixed, int shift,
+                                                  CandKey kp, int* __restrict__ hist, int maxblk,
+                                                  int* __restrict__ totals) {
+  const int m = record_count(counts, nh, cap, m_fixed);
   if ((int)blockIdx.x * TILE >= m) return;  // uniform
   __shared__ int h[256];
   h[threadIdx.x] = 0;
@@ -93,9 +110,8 @@ __global__ __launch_bounds__(ST) void k_sort_hist(const int4* __restrict__ in, i
 // in tiles before b), computed in place by a workgroup-wide scan of the row.
 __global__ __launch_bounds__(ST) void k_sort_offsets(int* __restrict__ hist, int maxblk,
                                                      const int* __restrict__ totals, int cap, int nh,
-                                                     const int32_t* __restrict__ counts) {
-  int off[9];
-  const int m = pack_offsets(counts, nh, cap, off);
+                                                     const int32_t* __restrict__ counts, int m_fixed) {
+  const int m = record_count(counts, nh, cap, m_fixed);
   const int nblk = (m + TILE - 1) / TILE;
   if (nblk == 0) return;
   __shared__ int sc[ST];
@@ -131,10 +147,10 @@ __global__ __launch_bounds__(ST) void k_sort_offsets(int* __restrict__ hist, int
 }
 
 __global__ __launch_bounds__(ST) void k_sort_scatter(const int4* __restrict__ in, int4* __restrict__ out, int cap,
-                                                     int nh, const int32_t* __restrict__ counts, int shift,
-                                                     CandKey kp, const int* __restrict__ offs, int maxblk) {
-  int off[9];
-  const int m = pack_offsets(counts, nh, cap, off);
+                                                     int nh, const int32_t* __restrict__ counts, int m_fixed,
+                                                     int shift, CandKey kp, const int* __restrict__ offs, int maxblk,
+                                                     int untag) {
+  const int m = record_count(counts, nh, cap, m_fixed);
   if ((int)blockIdx.x * TILE >= m) return;  // uniform
   __shared__ int base[256];      // running position per digit inside this tile's output range
   __shared__ int wcnt[ST / 64][256];
@@ -168,6 +184,7 @@ __global__ __launch_bounds__(ST) void k_sort_scatter(const int4* __restrict__ in
     if (valid) {
       int pos = base[d] + rank;
       for (int q = 0; q < w; ++q) pos += wcnt[q][d];
+      if (untag) rec.x &= 255;
       out[pos] = rec;
     }
     __syncthreads();
@@ -189,6 +206,32 @@ __global__ __launch_bounds__(ST) void k_sort_scatter(const int4* __restrict__ in
 __global__ void k_gather_counts(int32_t* const* __restrict__ ptrs, int count, int nh, int32_t* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count * nh) out[i] = ptrs[i / nh][i % nh];
+}
+
+// Batch pack: record i of the packed array belongs to the last trial whose
+// first record is <= i (empty trials share their successor's offset), then to
+// that trial's plane by its clamped counts.  The trial is tagged into the
+// harmonic field.  Block 0 also clears the per-pass digit totals.
+__global__ __launch_bounds__(ST) void k_sort_pack_batch(const RbTrial* __restrict__ tr, int count, int cap, int nh,
+                                                        int m, int4* __restrict__ out, int* __restrict__ totals,
+                                                        int ntotals) {
+  if (blockIdx.x == 0)
+    for (int t = threadIdx.x; t < ntotals; t += ST) totals[t] = 0;
+  const int i = blockIdx.x * ST + threadIdx.x;
+  if (i >= m) return;
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tr[mid].off <= (int64_t)i) lo = mid; else hi = mid - 1;
+  }
+  int off[9];
+  pack_offsets(tr[lo].counts, nh, cap, off);
+  const int j = i - (int)tr[lo].off;
+  int k = 0;
+  while (k + 1 < nh && j >= off[k + 1]) ++k;
+  int4 rec = tr[lo].cands[(size_t)k * cap + (j - off[k])];
+  rec.x |= lo << 8;
+  out[i] = rec;
 }
 
 // The ordered records and the counts written straight into page-locked host
@@ -235,16 +278,48 @@ hipError_t launch_sort_candidates(const fdas_cand* planes, int cap, int nh, cons
   const int passes = sort_passes(rows, bits_r);
   hipLaunchKernelGGL(k_sort_pack, dim3((maxm + ST - 1) / ST), dim3(ST), 0, s, reinterpret_cast<const int4*>(planes),
                      cap, nh, counts, reinterpret_cast<int4*>(a), totals, 256 * passes);
-  CandKey kp{rows, z_max, bits_r};
+  CandKey kp{rows, z_max, bits_r, 0};
   int4* src = reinterpret_cast<int4*>(a);
   int4* dst = reinterpret_cast<int4*>(b);
   for (int p = 0; p < passes; ++p) {
     const int shift = 8 * p;
     int* tot = totals + 256 * p;
-    hipLaunchKernelGGL(k_sort_hist, dim3(maxblk), dim3(ST), 0, s, src, cap, nh, counts, shift, kp, hist, maxblk, tot);
-    hipLaunchKernelGGL(k_sort_offsets, dim3(256), dim3(ST), 0, s, hist, maxblk, tot, cap, nh, counts);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(maxblk), dim3(ST), 0, s, src, dst, cap, nh, counts, shift, kp, hist,
-                       maxblk);
+    hipLaunchKernelGGL(k_sort_hist, dim3(maxblk), dim3(ST), 0, s, src, cap, nh, counts, -1, shift, kp, hist, maxblk,
+                       tot);
+    hipLaunchKernelGGL(k_sort_offsets, dim3(256), dim3(ST), 0, s, hist, maxblk, tot, cap, nh, counts, -1);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(maxblk), dim3(ST), 0, s, src, dst, cap, nh, counts, -1, shift, kp, hist,
+                       maxblk, 0);
+    int4* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  *sorted = reinterpret_cast<fdas_cand*>(src);
+  return hipGetLastError();
+}
+
+int sort_passes_batch(int count, int rows, int bits_r) {
+  const int slot_bits = 32 - __builtin_clz((unsigned)(8 * rows * count));  // trial * 8 * rows + plane slot
+  return (slot_bits + bits_r + 7) / 8;
+}
+
+hipError_t launch_sort_batch(const RbTrial* tab, int count, int cap, int nh, int m, int rows, int z_max, int bits_r,
+                             fdas_cand* a, fdas_cand* b, int* hist, int* totals, fdas_cand** sorted, hipStream_t s) {
+  *sorted = a;
+  if (m <= 0) return hipSuccess;
+  const int nblk = sort_tile_count(m);
+  const int passes = sort_passes_batch(count, rows, bits_r);
+  hipLaunchKernelGGL(k_sort_pack_batch, dim3((m + ST - 1) / ST), dim3(ST), 0, s, tab, count, cap, nh, m,
+                     reinterpret_cast<int4*>(a), totals, 256 * passes);
+  CandKey kp{rows, z_max, bits_r, 1};
+  int4* src = reinterpret_cast<int4*>(a);
+  int4* dst = reinterpret_cast<int4*>(b);
+  for (int p = 0; p < passes; ++p) {
+    const int shift = 8 * p;
+    int* tot = totals + 256 * p;
+    hipLaunchKernelGGL(k_sort_hist, dim3(nblk), dim3(ST), 0, s, src, cap, nh, nullptr, m, shift, kp, hist, nblk, tot);
+    hipLaunchKernelGGL(k_sort_offsets, dim3(256), dim3(ST), 0, s, hist, nblk, tot, cap, nh, nullptr, m);
+    hipLaunchKernelGGL(k_sort_scatter, dim3(nblk), dim3(ST), 0, s, src, dst, cap, nh, nullptr, m, shift, kp, hist,
+                       nblk, p == passes - 1 ? 1 : 0);
     int4* tmp = src;
     src = dst;
     dst = tmp;

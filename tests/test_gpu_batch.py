@@ -213,3 +213,39 @@ def test_batch_argument_errors():
     t = fdas.Tuning()
     t.overlap_groups = 9
     assert L.fdas_set_tuning(plan.handle, t) == fdas.ERR_INVALID_ARG
+
+
+def test_many_trials_in_one_readback():
+    # 300 trials (the trial number needs more than 8 bits of the sort tag),
+    # empty ones among them: every trial's list equals its single-call list
+    plan = fdas.plan_create(n_max=1 << 14, cand_capacity=4096)
+    try:
+        base = _specs([1, 3000, 9000], 310)
+        singles = [_single(plan, s) for s in base]
+        specs = [base[i % 3] for i in range(300)]
+        got, counts = Batch(plan, specs).run()
+        for i in range(300):
+            _, c1, hc1 = singles[i % 3]
+            _same(got[i], c1)
+            assert np.array_equal(counts[i], hc1)
+    finally:
+        plan.destroy()
+
+
+def test_short_host_buffer_truncates_the_last_trials():
+    plan = plan42()
+    specs = _specs([40000, 3000, 65536], 320)
+    b = Batch(plan, specs)
+    full, _ = b.run()
+    flat = np.concatenate(full)
+    assert flat.size > 10
+    short = flat.size - 7
+    got, _ = fdas.candidates_batch(plan, b.trials, capacity=short, allow_overflow=True)
+    _same(np.concatenate(got), flat[:short])
+    L = fdas.lib()
+    out = np.zeros(short, dtype=fdas.CAND_DTYPE)
+    offs = np.zeros(len(specs) + 1, dtype=np.int64)
+    st = L.fdas_candidates_batch(plan.handle, b.trials, len(specs), out.ctypes.data, short, offs.ctypes.data, None,
+                                 None)
+    assert st == fdas.ERR_CAPACITY
+    assert offs[-1] == short and np.all(np.diff(offs) >= 0)
