@@ -189,7 +189,7 @@ typedef struct {
 
 /* Launch parameters chosen by fdas_autotune (all fields 0 = built-in default). */
 typedef struct {
-  int32_t conv_templates_per_item; /* templates sharing one forward FFT (1..2*z_max+1) */
+  int32_t conv_templates_per_item; /* at most this many templates share one forward FFT (1..2*z_max+1; 0 = all of a chunk's templates in a workgroup's range) */
   int32_t conv_workgroups_per_cu;  /* resident convolution workgroups per compute unit (1..2) */
   int32_t overlap_groups;          /* trial groups whose harmonic sums overlap later convolutions (1..8) */
   int32_t emit_workgroups;         /* workgroups of the candidate-emission pass (64..16384) */

@@ -142,11 +142,9 @@ fdas_status plan_launch(fdas_plan* p, const fdas_trial* t, int count, Launch& L,
   const int rows = p->rows;
   const int V = p->geom.V;
   L.slots = p->tuning.conv_workgroups_per_cu > 0 ? p->tuning.conv_workgroups_per_cu * cu_count(p) : p->conv_slots;
-  int64_t chunks_total = 0;
-  for (int i = 0; i < count; ++i) chunks_total += (t[i].n + V - 1) / V;
-  L.tpg = p->tuning.conv_templates_per_item > 0 ? std::min(rows, p->tuning.conv_templates_per_item)
-                                                : ols_templates_per_item(chunks_total, rows, L.slots);
-  const int tgroups = (rows + L.tpg - 1) / L.tpg;
+  // 0: every workgroup's range of (chunk, template) pairs shares one forward
+  // FFT per chunk it touches
+  L.tpg = p->tuning.conv_templates_per_item > 0 ? std::min(rows, p->tuning.conv_templates_per_item) : 0;
   L.eblocks = p->tuning.emit_workgroups > 0 ? p->tuning.emit_workgroups : 1024;
   int64_t item = 0;
   int block = 0;
@@ -157,7 +155,7 @@ fdas_status plan_launch(fdas_plan* p, const fdas_trial* t, int count, Launch& L,
     if (e != hipSuccess) return hip_fail(e, "uploading a harmonic-sum tile order");
     ct[i] = ConvTrial{static_cast<const float2*>(t[i].d_spectrum), t[i].d_fop, t[i].n, t[i].ld, item};
     ht[i] = HsTrial{t[i].d_fop, t[i].ld, t[i].d_cands, t[i].d_counts, order, (int)t[i].n, block, nblocks, 0};
-    item += ((t[i].n + V - 1) / V) * tgroups;
+    item += ((t[i].n + V - 1) / V) * rows;
     block += nblocks;  // a multiple of 8: every trial starts on XCD 0
   }
   // contiguous groups of about equal total length

@@ -50,22 +50,20 @@ hipError_t launch_ols_conv_list(const float2* x, int64_t n, float* fop, int64_t 
                                 const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
                                 const int* chunk_list, int nlist, hipStream_t s);
 
-// Templates sharing one forward FFT, chosen by a cost model for a queue of
-// items_per_template chunks run on `slots` resident workgroups.
-int ols_templates_per_item(int64_t items_per_template, int rows, int slots);
-
 // One spectrum of a batch for the convolution queue (device table entry).
 struct ConvTrial {
   const float2* x;
   float* fop;
   int64_t n;
   int64_t ld;
-  int64_t item0;  // first queue item of this trial
+  int64_t item0;  // first (chunk, template) pair of this trial: pairs before it = sum of chunks * rows
 };
 
-// Queue items [item_begin, item_end) of a batch; tpg templates per item.
+// (chunk, template) pairs [item_begin, item_end) of a batch, split into equal
+// contiguous ranges over the resident workgroups; at most tmax templates share
+// one forward FFT (0: a whole chunk's templates).
 hipError_t launch_ols_conv_batch(const ConvTrial* trials, int ntrials, int64_t item_begin, int64_t item_end,
-                                 const float2* H, const float2* tw1, const float2* tw2, int rows, int tpg,
+                                 const float2* H, const float2* tw1, const float2* tw2, int rows, int tmax,
                                  const OlsGeom& g, int slots, hipStream_t s);
 
 // Split 16-bit form of the packed operand: templates ordered and tiled as in

@@ -231,110 +231,112 @@ __device__ __forceinline__ void load_twiddles(const float2* __restrict__ tw1tab,
   }
 }
 
-// Persistent grid: work item = (chunk, template group), item = chunk * groups + group,
-// visited with stride gridDim.x.
+// Work split of the persistent grid.  The (chunk, template) pairs, chunk-major
+// (pair q = chunk * rows + z), are cut into gridDim.x contiguous ranges of
+// equal length; a workgroup transforms a chunk forward once for every chunk its
+// range touches (at most tmax templates per forward transform).  Every
+// workgroup does the same number of inverse transforms plus two or three
+// forward ones, so the grid finishes together.
+__device__ __forceinline__ void pair_range(int64_t total, int64_t& lo, int64_t& hi) {
+  lo = total * (int64_t)blockIdx.x / (int64_t)gridDim.x;
+  hi = total * ((int64_t)blockIdx.x + 1) / (int64_t)gridDim.x;
+}
+
+// templates [z_lo, z_hi) of the piece of the range [q, hi) that starts at pair q
+__device__ __forceinline__ int piece_end(int64_t q, int64_t hi, int z_lo, int rows, int tmax) {
+  return (int)min((int64_t)min(rows, z_lo + tmax), (int64_t)z_lo + (hi - q));
+}
+
 __global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x, int64_t n,
                                                     float* __restrict__ fop, int64_t ld,
                                                     const float2* __restrict__ H,
                                                     const float2* __restrict__ tw1tab,
-                                                    const float2* __restrict__ tw2tab, int rows,
-                                                    int tpg, int groups, int64_t items, int V, int P) {
+                                                    const float2* __restrict__ tw2tab, int rows, int tmax,
+                                                    int64_t chunks, int V, int P) {
   __shared__ float2 buf1[16 * RS];
   __shared__ float2 buf2[16 * RS];
   const int tid = threadIdx.x;
   float2 tw1[15], tw2[15];
   load_twiddles(tw1tab, tw2tab, tw1, tw2, tid);
-  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const int64_t chunk = item / groups;
-    const int grp = (int)(item - chunk * groups);
-    const int z_lo = grp * tpg;
-    ols_item(x, n, fop, ld, H, chunk, z_lo, min(rows, z_lo + tpg), V, P, tw1, tw2, buf1, buf2, tid);
+  int64_t q, hi;
+  pair_range(chunks * rows, q, hi);
+  while (q < hi) {
+    const int64_t chunk = q / rows;
+    const int z_lo = (int)(q - chunk * rows);
+    const int z_hi = piece_end(q, hi, z_lo, rows, tmax);
+    ols_item(x, n, fop, ld, H, chunk, z_lo, z_hi, V, P, tw1, tw2, buf1, buf2, tid);
+    q += z_hi - z_lo;
   }
 }
 
-// Listed chunks only: item = i * groups + group over chunk_list[0 .. nlist).
+// Listed chunks only: pair q = i * rows + z over chunk_list[0 .. nlist).
 __global__ __launch_bounds__(NT, 2) void k_ols_conv_list(const float2* __restrict__ x, int64_t n,
                                                          float* __restrict__ fop, int64_t ld,
                                                          const float2* __restrict__ H,
                                                          const float2* __restrict__ tw1tab,
-                                                         const float2* __restrict__ tw2tab, int rows, int tpg,
-                                                         int groups, const int* __restrict__ chunk_list, int nlist,
-                                                         int V, int P) {
+                                                         const float2* __restrict__ tw2tab, int rows, int tmax,
+                                                         const int* __restrict__ chunk_list, int nlist, int V,
+                                                         int P) {
   __shared__ float2 buf1[16 * RS];
   __shared__ float2 buf2[16 * RS];
   const int tid = threadIdx.x;
   float2 tw1[15], tw2[15];
   load_twiddles(tw1tab, tw2tab, tw1, tw2, tid);
-  const int64_t items = (int64_t)nlist * groups;
-  for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
-    const int64_t li = item / groups;
-    const int grp = (int)(item - li * groups);
-    const int z_lo = grp * tpg;
-    ols_item(x, n, fop, ld, H, chunk_list[li], z_lo, min(rows, z_lo + tpg), V, P, tw1, tw2, buf1, buf2, tid);
+  int64_t q, hi;
+  pair_range((int64_t)nlist * rows, q, hi);
+  while (q < hi) {
+    const int64_t li = q / rows;
+    const int z_lo = (int)(q - li * rows);
+    const int z_hi = piece_end(q, hi, z_lo, rows, tmax);
+    ols_item(x, n, fop, ld, H, chunk_list[li], z_lo, z_hi, V, P, tw1, tw2, buf1, buf2, tid);
+    q += z_hi - z_lo;
   }
 }
 
-// Batch of spectra: one queue of (trial, chunk, template group) items.  Trial t
-// owns items [trials[t].item0, trials[t+1].item0); this launch works through
-// items [item_begin, item_end) with stride gridDim.x.
+// Batch of spectra: trial t owns pairs [trials[t].item0, trials[t+1].item0)
+// (its chunks x rows); this launch splits pairs [item_begin, item_end).  A
+// piece never crosses a chunk, hence never a trial.
 __global__ __launch_bounds__(NT, 2) void k_ols_conv_batch(const ConvTrial* __restrict__ trials, int ntrials,
                                                           int64_t item_begin, int64_t item_end,
                                                           const float2* __restrict__ H,
                                                           const float2* __restrict__ tw1tab,
-                                                          const float2* __restrict__ tw2tab, int rows, int tpg,
-                                                          int groups, int V, int P) {
+                                                          const float2* __restrict__ tw2tab, int rows, int tmax,
+                                                          int V, int P) {
   __shared__ float2 buf1[16 * RS];
   __shared__ float2 buf2[16 * RS];
   const int tid = threadIdx.x;
   float2 tw1[15], tw2[15];
   load_twiddles(tw1tab, tw2tab, tw1, tw2, tid);
-  for (int64_t item = item_begin + blockIdx.x; item < item_end; item += gridDim.x) {
-    // last trial whose first item is <= item (uniform across the workgroup)
-    int lo = 0, hi = ntrials - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (trials[mid].item0 <= item) lo = mid; else hi = mid - 1;
+  int64_t q, hi;
+  pair_range(item_end - item_begin, q, hi);
+  q += item_begin;
+  hi += item_begin;
+  while (q < hi) {
+    // last trial whose first pair is <= q (uniform across the workgroup)
+    int lo = 0, up = ntrials - 1;
+    while (lo < up) {
+      const int mid = (lo + up + 1) >> 1;
+      if (trials[mid].item0 <= q) lo = mid; else up = mid - 1;
     }
     const ConvTrial tr = trials[lo];
-    const int64_t local = item - tr.item0;
-    const int64_t chunk = local / groups;
-    const int grp = (int)(local - chunk * groups);
-    const int z_lo = grp * tpg;
-    ols_item(tr.x, tr.n, tr.fop, tr.ld, H, chunk, z_lo, min(rows, z_lo + tpg), V, P, tw1, tw2, buf1, buf2, tid);
+    const int64_t local = q - tr.item0;
+    const int64_t chunk = local / rows;
+    const int z_lo = (int)(local - chunk * rows);
+    const int z_hi = piece_end(q, hi, z_lo, rows, tmax);
+    ols_item(tr.x, tr.n, tr.fop, tr.ld, H, chunk, z_lo, z_hi, V, P, tw1, tw2, buf1, buf2, tid);
+    q += z_hi - z_lo;
   }
 }
 
 }  // namespace
 
-int ols_templates_per_item(int64_t items_per_template, int rows, int slots) {
-  // Every work item pays one forward FFT plus tpg inverse FFTs, and items run
-  // in rounds of `slots` resident workgroups: minimise rounds * (tpg + 1).
-  int best_tpg = rows;
-  double best = 1e300;
-  for (int G = 1; G <= rows; ++G) {
-    const int tpg = (rows + G - 1) / G;
-    const int groups = (rows + tpg - 1) / tpg;
-    const int64_t items = items_per_template * groups;
-    const int64_t rounds = (items + slots - 1) / slots;
-    const double cost = (double)rounds * (tpg + 1);
-    if (cost < best - 1e-9) {
-      best = cost;
-      best_tpg = tpg;
-    }
-  }
-  return best_tpg;
-}
-
 hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
                            const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
                            hipStream_t s) {
   const int64_t chunks = (n + g.V - 1) / g.V;
-  const int tpg = ols_templates_per_item(chunks, rows, slots);
-  const int groups = (rows + tpg - 1) / tpg;
-  const int64_t items = chunks * groups;
-  const unsigned grid = (unsigned)std::min<int64_t>(items, slots);
-  hipLaunchKernelGGL(k_ols_conv, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, tpg, groups, items,
-                     g.V, g.P);
+  const unsigned grid = (unsigned)std::min<int64_t>(chunks * rows, slots);
+  hipLaunchKernelGGL(k_ols_conv, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, rows, chunks, g.V,
+                     g.P);
   return hipGetLastError();
 }
 
@@ -342,23 +344,19 @@ hipError_t launch_ols_conv_list(const float2* x, int64_t n, float* fop, int64_t 
                                 const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
                                 const int* chunk_list, int nlist, hipStream_t s) {
   if (nlist <= 0) return hipSuccess;
-  const int tpg = ols_templates_per_item(nlist, rows, slots);
-  const int groups = (rows + tpg - 1) / tpg;
-  const int64_t items = (int64_t)nlist * groups;
-  const unsigned grid = (unsigned)std::min<int64_t>(items, slots);
-  hipLaunchKernelGGL(k_ols_conv_list, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, tpg, groups,
-                     chunk_list, nlist, g.V, g.P);
+  const unsigned grid = (unsigned)std::min<int64_t>((int64_t)nlist * rows, slots);
+  hipLaunchKernelGGL(k_ols_conv_list, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, rows, chunk_list,
+                     nlist, g.V, g.P);
   return hipGetLastError();
 }
 
 hipError_t launch_ols_conv_batch(const ConvTrial* trials, int ntrials, int64_t item_begin, int64_t item_end,
-                                 const float2* H, const float2* tw1, const float2* tw2, int rows, int tpg,
+                                 const float2* H, const float2* tw1, const float2* tw2, int rows, int tmax,
                                  const OlsGeom& g, int slots, hipStream_t s) {
   if (item_end <= item_begin) return hipSuccess;
-  const int groups = (rows + tpg - 1) / tpg;
   const unsigned grid = (unsigned)std::min<int64_t>(item_end - item_begin, slots);
   hipLaunchKernelGGL(k_ols_conv_batch, dim3(grid), dim3(NT), 0, s, trials, ntrials, item_begin, item_end, H, tw1,
-                     tw2, rows, tpg, groups, g.V, g.P);
+                     tw2, rows, tmax > 0 ? std::min(tmax, rows) : rows, g.V, g.P);
   return hipGetLastError();
 }
 
