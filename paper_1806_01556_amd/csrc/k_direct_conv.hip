@@ -34,6 +34,15 @@
 namespace fdas {
 namespace {
 
+// Two adjacent FOP values stored non-temporally: the plane is written once and
+// read back only after the whole convolution, so it should not stay in the
+// caches (the same policy as the overlap-save kernel's stores).
+__device__ __forceinline__ void store2_nt(float* dst, float a, float b) {
+  typedef float f2v __attribute__((ext_vector_type(2)));
+  const f2v v = {a, b};
+  __builtin_nontemporal_store(v, reinterpret_cast<f2v*>(dst));
+}
+
 constexpr int DW = 4;                 // waves per workgroup
 constexpr int SUB = 8;                // 16-bin sub-tiles per wave
 constexpr int WAVE_BINS = 16 * SUB;   // 128
@@ -122,9 +131,9 @@ __global__ __launch_bounds__(DW * 64) void k_direct_conv(const float2* __restric
         const float p0 = c ? pw[2] : pw[0];
         const float p1 = c ? pw[3] : pw[1];
         if (j + 2 <= n) {
-          *reinterpret_cast<float2*>(dst) = make_float2(p0, p1);
+          store2_nt(dst, p0, p1);
         } else if (j < n) {
-          dst[0] = p0;
+          __builtin_nontemporal_store(p0, dst);
         }
       }
     }
@@ -290,9 +299,9 @@ __global__ __launch_bounds__(DW * 64) void k_direct_conv_split(const float2* __r
         const float p0 = c ? pw[2] : pw[0];
         const float p1 = c ? pw[3] : pw[1];
         if (j + 2 <= n) {
-          *reinterpret_cast<float2*>(dst) = make_float2(p0, p1);
+          store2_nt(dst, p0, p1);
         } else if (j < n) {
-          dst[0] = p0;
+          __builtin_nontemporal_store(p0, dst);
         }
       }
     }
