@@ -530,34 +530,43 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_emit(const float* __rest
 #pragma unroll
         for (int a = 0; a < 4; ++a) hk[m][a] = hk[m - 1][a] + src[m][a];
     }
+    // per plane: this lane's hit count (0..4) as three ballots, the wave total
+    // and this lane's offset; then lane m - 1 reserves plane m's slots, all
+    // planes in one round of atomics
+    unsigned hits = 0u;  // bit 4 * (m - 1) + a: column j0 + a is a candidate of plane m
+    int below_m[NH + 1], total[NH + 1];
+    auto below = [&](unsigned long long b) {
+      return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+    };
+    int mine = 0;
 #pragma unroll
     for (int m = 1; m <= NH; ++m) {
       int c = 0;
-      float t = 0.0f;
-      if (act) {
-        t = ta[(m - 1) * ROWS + r];
+      const float t = act ? ta[(m - 1) * ROWS + r] : 0.0f;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) c += (j0 + a < n && hk[m][a] > t) ? 1 : 0;
+      for (int a = 0; a < 4; ++a) {
+        const bool h = act && j0 + a < n && hk[m][a] > t;
+        hits |= h ? 1u << (4 * (m - 1) + a) : 0u;
+        c += h ? 1 : 0;
       }
       const unsigned long long b0 = __ballot(c & 1), b1 = __ballot(c & 2), b2 = __ballot(c & 4);
-      const int total = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
-      if (total == 0) continue;  // uniform
-      int base = 0;
-      if (lane == 0) base = atomicAdd(&counts[m - 1], total);
-      base = __shfl(base, 0);
-      auto below = [&](unsigned long long b) {
-        return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
-      };
-      int slot = base + below(b0) + 2 * below(b1) + 4 * below(b2);
-      if (c) {
+      total[m] = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+      below_m[m] = below(b0) + 2 * below(b1) + 4 * below(b2);
+      if (lane == m - 1) mine = total[m];
+    }
+    int base = 0;
+    if (lane < NH && mine > 0) base = atomicAdd(&counts[lane], mine);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          if (j0 + a < n && hk[m][a] > t) {
-            if (slot < cap)
-              *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
-                  make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
-            ++slot;
-          }
+    for (int m = 1; m <= NH; ++m) {
+      if (total[m] == 0) continue;  // uniform
+      int slot = __shfl(base, m - 1) + below_m[m];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        if ((hits >> (4 * (m - 1) + a)) & 1u) {
+          if (slot < cap)
+            *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
+                make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
+          ++slot;
         }
       }
     }
