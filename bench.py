@@ -355,6 +355,11 @@ def main():
     ap.add_argument("--method", choices=("ols", "direct", "direct-fp16", "direct-bf16"), default="ols",
                     help="FT-convolution method: overlap-save FFT (default, the faster) or the direct "
                          "correlation on the matrix cores")
+    ap.add_argument("--readback", choices=["auto", "mapped", "copy"], default="auto",
+                    help="candidate readback: fdas_candidates_mapped (a kernel writes to pinned memory, one "
+                         "wait) or fdas_candidates (DMA copy, two waits); auto = copy with steps in flight "
+                         "(no compute units held by PCIe writes beside the next step's kernels), mapped "
+                         "otherwise")
     ap.add_argument("--pipeline", type=int, default=2,
                     help="steps in flight in the timed region: with 2 (default), step k+1's kernels are "
                          "queued on a second plan and stream before step k's candidates are read back; "
@@ -418,10 +423,17 @@ def main():
         if ev:
             ev[2].record(st)
 
+    # mapped: the ordered records are written into page-locked host memory by
+    # a kernel (one wait); copy: a DMA copy after a wait for the counts (two
+    # waits, no compute units busy with PCIe writes)
+    if args.readback == "auto":
+        args.readback = "copy" if P > 1 else "mapped"
+    rb_cap = None if args.readback == "mapped" else plans[0].desc.n_harm * plans[0].desc.cand_capacity
+
     def readback(k, P=P):
         i = k % P
-        return fdas.candidates(plans[i], bufs[i][0], bufs[i][1], stream=streams[i], allow_overflow=True,
-                               copy=False)
+        return fdas.candidates(plans[i], bufs[i][0], bufs[i][1], capacity=rb_cap, stream=streams[i],
+                               allow_overflow=True, copy=False)
 
     def run(steps, evs=None, P=P):
         out = None
@@ -542,7 +554,7 @@ def main():
                    "method": {"ols": "ols_fft_c4096", "direct": "direct_mfma_fp32",
                               "direct-fp16": "direct_mfma_split_fp16",
                               "direct-bf16": "direct_mfma_split_bf16"}[args.method],
-                   "pipeline": P},
+                   "pipeline": P, "readback": args.readback},
         "roofline": roof,
         "roofline_isolated": roof_iso,
         "stages_ms": {"convolve": round(conv_ms, 4), "harmonic_sum": round(hs_ms, 4),
