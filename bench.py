@@ -536,6 +536,16 @@ def main():
                 "note": "serial pass; the headline roofline times the kernel while the other step's "
                         "kernels may share the GPU"}
 
+    if args.method in ("direct-fp16", "direct-bf16"):
+        # matrix-core work the split kernel issues: its 11 template tiles
+        # (85 templates by |z|, 8 per tile, each over the union of its
+        # members' supports padded to 8 tap pairs) make 163 groups of 16 taps
+        # per 16 bins, each 3 v_mfma_f32_16x16x32 of 16,384 flop
+        issued = 163 * 3 * 16384 / 16 * n
+        issued_tf = issued / (conv_ms * 1e-3) / 1e12
+        roof["mfma_issued"] = {"achieved": round(issued_tf, 3), "peak": FP16_MATRIX_PEAK_TF, "unit": "TFLOP/s",
+                               "frac": round(issued_tf / FP16_MATRIX_PEAK_TF, 4),
+                               "note": "hi*hi + hi*lo + lo*hi products and padded taps included"}
     out = {
         "metric": METRIC,
         "value": round(args.steps / wall, 3),
