@@ -41,10 +41,17 @@ FP32_MATRIX_PEAK_TF = 157.3  # MI355X FP32 matrix (dense), published
 FP16_MATRIX_PEAK_TF = 2500.0  # MI355X FP16 / BF16 matrix (dense), published
 
 
+# headers whose code is compiled into a kernel file's kernels
+KERNEL_HEADERS = {"k_ols_conv.hip": ["fft16.h"]}
+
+
 def kernel_source_digest(name):
-    path = os.path.join(ROOT, "paper_1806_01556_amd", "csrc", name)
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] of a kernel source and of the headers its kernels inline."""
+    h = hashlib.sha256()
+    for f in [name] + KERNEL_HEADERS.get(name, []):
+        with open(os.path.join(ROOT, "paper_1806_01556_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def read_traffic(kernel_file, launches_bytes_key):
