@@ -482,10 +482,79 @@ __device__ __forceinline__ void hs_emit_row(const float* __restrict__ fop, int64
   }
 }
 
+// Phase 2 for one wave: every active lane re-forms the sums of its row r of
+// columns j0..j0+3 (same k order as phase 1, so bit-identical) and the wave
+// appends the candidates of all lanes to one plane set (fop, cands, counts
+// uniform across the wave).  Each plane's slots are reserved for the whole
+// wave in one round of atomics: lane m - 1 reserves plane m, lane offsets come
+// from ballots of the 3-bit per-lane counts.
+template <int Z, int NH>
+__device__ __forceinline__ void hs_emit_wave(const float* __restrict__ fop, int64_t ld, int n, int j0, int r,
+                                             bool act, const float* __restrict__ ta,
+                                             fdas_cand* __restrict__ cands, int cap,
+                                             int32_t* __restrict__ counts, int lane) {
+  constexpr int ROWS = 2 * Z + 1;
+  const int i = r - Z;
+  float hk[NH + 1][4];
+  if (act) {
+    const float4 v = *reinterpret_cast<const float4*>(fop + (size_t)r * ld + j0);
+    float src[NH + 1][4];
+#pragma unroll
+    for (int m = 2; m <= NH; ++m) {
+      const float* rowp = fop + (size_t)(i / m + Z) * ld;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) src[m][a] = rowp[(j0 + a) / m];
+    }
+    hk[1][0] = v.x;
+    hk[1][1] = v.y;
+    hk[1][2] = v.z;
+    hk[1][3] = v.w;
+#pragma unroll
+    for (int m = 2; m <= NH; ++m)
+#pragma unroll
+      for (int a = 0; a < 4; ++a) hk[m][a] = hk[m - 1][a] + src[m][a];
+  }
+  unsigned hits = 0u;  // bit 4 * (m - 1) + a: column j0 + a is a candidate of plane m
+  int below_m[NH + 1], total[NH + 1];
+  auto below = [&](unsigned long long b) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+  };
+  int mine = 0;
+#pragma unroll
+  for (int m = 1; m <= NH; ++m) {
+    int c = 0;
+    const float t = act ? ta[(m - 1) * ROWS + r] : 0.0f;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      const bool h = act && j0 + a < n && hk[m][a] > t;
+      hits |= h ? 1u << (4 * (m - 1) + a) : 0u;
+      c += h ? 1 : 0;
+    }
+    const unsigned long long b0 = __ballot(c & 1), b1 = __ballot(c & 2), b2 = __ballot(c & 4);
+    total[m] = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+    below_m[m] = below(b0) + 2 * below(b1) + 4 * below(b2);
+    if (lane == m - 1) mine = total[m];
+  }
+  int base = 0;
+  if (lane < NH && mine > 0) base = atomicAdd(&counts[lane], mine);
+#pragma unroll
+  for (int m = 1; m <= NH; ++m) {
+    if (total[m] == 0) continue;  // uniform
+    int slot = __shfl(base, m - 1) + below_m[m];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+      if ((hits >> (4 * (m - 1) + a)) & 1u) {
+        if (slot < cap)
+          *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
+              make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
+        ++slot;
+      }
+    }
+  }
+}
+
 // Phase 2: work item w = entry * ROWS + row, grid-stride over all items in
-// wave-uniform steps so the whole wave reaches the compaction together: each
-// plane's slots are reserved with one atomic per wave (lane offsets from
-// ballots of the 3-bit per-lane counts), not one per lane.
+// wave-uniform steps so the whole wave reaches the compaction together.
 template <int Z, int NH>
 __global__ __launch_bounds__(HS_THREADS) void k_harmsum_emit(const float* __restrict__ fop, int64_t ld, int n,
                                                              const int4* __restrict__ hitrows,
@@ -509,67 +578,7 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_emit(const float* __rest
       act = ((word >> (r % 32)) & 1u) != 0;
     }
     if (__ballot(act) == 0ull) continue;  // uniform
-    const int j0 = ent.x;
-    const int i = r - Z;
-    float hk[NH + 1][4];
-    if (act) {
-      const float4 v = *reinterpret_cast<const float4*>(fop + (size_t)r * ld + j0);
-      float src[NH + 1][4];
-#pragma unroll
-      for (int m = 2; m <= NH; ++m) {
-        const float* rowp = fop + (size_t)(i / m + Z) * ld;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) src[m][a] = rowp[(j0 + a) / m];
-      }
-      hk[1][0] = v.x;
-      hk[1][1] = v.y;
-      hk[1][2] = v.z;
-      hk[1][3] = v.w;
-#pragma unroll
-      for (int m = 2; m <= NH; ++m)
-#pragma unroll
-        for (int a = 0; a < 4; ++a) hk[m][a] = hk[m - 1][a] + src[m][a];
-    }
-    // per plane: this lane's hit count (0..4) as three ballots, the wave total
-    // and this lane's offset; then lane m - 1 reserves plane m's slots, all
-    // planes in one round of atomics
-    unsigned hits = 0u;  // bit 4 * (m - 1) + a: column j0 + a is a candidate of plane m
-    int below_m[NH + 1], total[NH + 1];
-    auto below = [&](unsigned long long b) {
-      return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
-    };
-    int mine = 0;
-#pragma unroll
-    for (int m = 1; m <= NH; ++m) {
-      int c = 0;
-      const float t = act ? ta[(m - 1) * ROWS + r] : 0.0f;
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const bool h = act && j0 + a < n && hk[m][a] > t;
-        hits |= h ? 1u << (4 * (m - 1) + a) : 0u;
-        c += h ? 1 : 0;
-      }
-      const unsigned long long b0 = __ballot(c & 1), b1 = __ballot(c & 2), b2 = __ballot(c & 4);
-      total[m] = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
-      below_m[m] = below(b0) + 2 * below(b1) + 4 * below(b2);
-      if (lane == m - 1) mine = total[m];
-    }
-    int base = 0;
-    if (lane < NH && mine > 0) base = atomicAdd(&counts[lane], mine);
-#pragma unroll
-    for (int m = 1; m <= NH; ++m) {
-      if (total[m] == 0) continue;  // uniform
-      int slot = __shfl(base, m - 1) + below_m[m];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        if ((hits >> (4 * (m - 1) + a)) & 1u) {
-          if (slot < cap)
-            *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
-                make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
-          ++slot;
-        }
-      }
-    }
+    hs_emit_wave<Z, NH>(fop, ld, n, ent.x, r, act, ta, cands, cap, counts, lane);
   }
 }
 
@@ -588,15 +597,35 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_emit_batch(const HsTrial
                                                                    const float* __restrict__ ta, int cap) {
   constexpr int ROWS = 2 * Z + 1;
   const int64_t items = (int64_t)(*hitrow_count) * ROWS;
-  for (int64_t w = (int64_t)blockIdx.x * HS_THREADS + threadIdx.x; w < items;
-       w += (int64_t)gridDim.x * HS_THREADS) {
-    const int4 ent = hitrows[w / ROWS];
-    const int r = (int)(w % ROWS);
-    const unsigned w2 = (unsigned)ent.w & 0x1FFFFFu;
-    const unsigned word = (unsigned)(r < 32 ? ent.y : (r < 64 ? ent.z : (int)w2));
-    if (!((word >> (r % 32)) & 1u)) continue;
-    const HsTrial& tr = trials[(unsigned)ent.w >> 21];
-    hs_emit_row<Z, NH>(tr.fop, tr.ld, tr.n, ent.x, r, ta, tr.cands, cap, tr.counts);
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * HS_THREADS;
+  // wave-uniform steps; a wave whose active lanes all belong to one trial (the
+  // usual case: a phase-1 block appends its entries together) reserves slots
+  // per plane for the whole wave, a mixed wave falls back to one atomic per
+  // lane and plane
+  for (int64_t w0 = (int64_t)blockIdx.x * HS_THREADS + (threadIdx.x & ~63); w0 < items; w0 += stride) {
+    const int64_t w = w0 + lane;
+    bool act = w < items;
+    int4 ent = make_int4(0, 0, 0, 0);
+    int r = 0;
+    if (act) {
+      ent = hitrows[w / ROWS];
+      r = (int)(w % ROWS);
+      const unsigned w2 = (unsigned)ent.w & 0x1FFFFFu;
+      const unsigned word = (unsigned)(r < 32 ? ent.y : (r < 64 ? ent.z : (int)w2));
+      act = ((word >> (r % 32)) & 1u) != 0;
+    }
+    const unsigned long long am = __ballot(act);
+    if (am == 0ull) continue;  // uniform
+    const int tri = (int)((unsigned)ent.w >> 21);
+    const int lead = __builtin_amdgcn_readlane(tri, (int)__builtin_ctzll(am));
+    if (__ballot(act && tri != lead) == 0ull) {  // uniform
+      const HsTrial& tr = trials[lead];
+      hs_emit_wave<Z, NH>(tr.fop, tr.ld, tr.n, ent.x, r, act, ta, tr.cands, cap, tr.counts, lane);
+    } else if (act) {
+      const HsTrial& tr = trials[tri];
+      hs_emit_row<Z, NH>(tr.fop, tr.ld, tr.n, ent.x, r, ta, tr.cands, cap, tr.counts);
+    }
   }
 }
 
