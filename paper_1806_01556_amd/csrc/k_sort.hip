@@ -91,13 +91,22 @@ __global__ __launch_bounds__(ST) void k_sort_hist(const int4* __restrict__ in, i
   h[threadIdx.x] = 0;
   __syncthreads();
   const int base = blockIdx.x * TILE;
+  // one LDS atomic per distinct digit of a wave (lanes with equal digits found
+  // by ballots, as in the scatter): skewed digits -- the trial and plane bits
+  // of the top passes -- would otherwise serialise 64 atomics on one address
 #pragma unroll
   for (int j = 0; j < SPT; ++j) {
     const int i = base + j * ST + threadIdx.x;
-    if (i < m) {
-      const int d = (int)((cand_key(in[i], kp) >> shift) & 255ull);
-      atomicAdd(&h[d], 1);
+    const bool valid = i < m;
+    const int d = valid ? (int)((cand_key(in[i], kp) >> shift) & 255ull) : 0;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const unsigned long long m1 = __ballot((d >> b) & 1);
+      peers &= ((d >> b) & 1) ? m1 : ~m1;
     }
+    const int rank = __builtin_amdgcn_mbcnt_hi((unsigned)(peers >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)peers, 0u));
+    if (valid && rank == 0) atomicAdd(&h[d], __popcll(peers));
   }
   __syncthreads();
   const int v = h[threadIdx.x];
