@@ -372,8 +372,8 @@ def main():
                          "queued on a second plan and stream before step k's candidates are read back; "
                          "1 runs one step after the other")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="after timing, copy the FOP buffer 3 times (a plain copy of known size, "
-                         "so HBM counters can be scaled to bytes)")
+                    help="label the FOP-buffer copies made after timing (4 plain copies of known size, "
+                         "also timed as the achievable HBM bandwidth) so HBM counters can be scaled to bytes")
     ap.add_argument("--workload", choices=("ska", "batch", "prescreen"), default="ska",
                     help="ska: one 2^22-bin spectrum per step (the headline); batch: 64 dispersion trials of "
                          "uneven length per step through the batch calls; prescreen: train the learned block "
@@ -576,6 +576,8 @@ def main():
         "roofline_isolated": roof_iso,
         "stages_ms": {"convolve": round(conv_ms, 4), "harmonic_sum": round(hs_ms, 4),
                       "candidates_readback_not_overlapped": round(readback_ms, 4)},
+        "stages_median_ms": {"convolve": round(float(np.median([e[0].elapsed_time(e[1]) for e in evs])), 4),
+                             "harmonic_sum": round(float(np.median([e[1].elapsed_time(e[2]) for e in evs])), 4)},
         "serial_ms_per_step": round(serial_ms, 4),
         "pipelined_2": pipe,
         "serial_stages_ms": {"convolve": round(conv_ms_serial, 4), "harmonic_sum": round(hs_ms_serial, 4)},
@@ -586,14 +588,24 @@ def main():
         "candidates": ncand,
         "candidates_per_plane": [int(v) for v in hc],
     }
+    # achievable HBM bandwidth beside the 8 TB/s spec: a plain device copy of
+    # the FOP buffer (read + write), after the timed region; with
+    # --calibrate-copy the same copies scale the HBM counters
+    src = fops[0].view(-1)
+    dst = torch.empty_like(src)
+    ce = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    dst.copy_(src)
+    ce[0].record()
+    for _ in range(3):
+        dst.copy_(src)
+    ce[1].record()
+    torch.cuda.synchronize()
+    copy_ms = ce[0].elapsed_time(ce[1]) / 3
+    out["hbm_copy"] = {"bytes": 2 * src.numel() * 4, "ms": round(copy_ms, 4),
+                       "gbs": round(2 * src.numel() * 4 / (copy_ms * 1e-3) / 1e9, 1)}
     if args.calibrate_copy:
-        src = fops[0].view(-1)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
         out["calibration_copy_bytes"] = {"read": src.numel() * 4, "write": src.numel() * 4}
-        del dst
+    del dst
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(spec, n)
     for pl in plans:
