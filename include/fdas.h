@@ -279,6 +279,20 @@ fdas_status fdas_search_blocks(fdas_plan* plan, const void* d_spectrum, int64_t 
                                const int32_t* h_blocks, int32_t nblocks, fdas_cand* d_cands, int32_t* d_counts,
                                void* stream);
 
+/* The same restricted search with the block selection on the device, so
+ * nothing waits for the host between the pre-screen and the search: blocks b
+ * with d_logits[b] > threshold (d_logits: float[ceil(n/4096)] on the device,
+ * e.g. written by fdas_prescreen_forward over blocks 0, 1, ...; NaN never
+ * flags) and their harmonic closure -- the blocks [m b, m (b + 1) - 1],
+ * m = 2..n_harm, holding the multiples m j of their columns -- are searched
+ * exactly as fdas_search_blocks searches that block list (identical
+ * candidates and powers).  n <= 16384 * 4096 bins.  The plan keeps device
+ * lists sized for the spectrum.  Plans other than overlap-save / 85 rows /
+ * stretch search the whole spectrum.  Asynchronous on stream. */
+fdas_status fdas_search_flagged(fdas_plan* plan, const void* d_spectrum, int64_t n, float* d_fop, int64_t ld,
+                                const float* d_logits, float threshold, fdas_cand* d_cands, int32_t* d_counts,
+                                void* stream);
+
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* fdas_last_error(void);
 

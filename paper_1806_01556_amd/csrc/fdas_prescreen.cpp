@@ -293,4 +293,63 @@ fdas_status fdas_search_blocks(fdas_plan* p, const void* d_spectrum, int64_t n, 
   return ok();
 }
 
+fdas_status fdas_search_flagged(fdas_plan* p, const void* d_spectrum, int64_t n, float* d_fop, int64_t ld,
+                                const float* d_logits, float threshold, fdas_cand* d_cands, int32_t* d_counts,
+                                void* stream) {
+  if (!p) return fail(FDAS_ERR_INVALID_ARG, "plan is NULL");
+  if (!d_spectrum || reinterpret_cast<uintptr_t>(d_spectrum) % 8 != 0)
+    return fail(FDAS_ERR_INVALID_ARG, "spectrum pointer is NULL or not 8-byte aligned");
+  fdas_status st = check_fop_args(p, d_fop, n, ld);
+  if (st != FDAS_OK) return st;
+  if (!d_cands || reinterpret_cast<uintptr_t>(d_cands) % 16 != 0 || !d_counts)
+    return fail(FDAS_ERR_INVALID_ARG, "candidate buffers are NULL or misaligned");
+  if (!d_logits || reinterpret_cast<uintptr_t>(d_logits) % 4 != 0)
+    return fail(FDAS_ERR_INVALID_ARG, "logits pointer is NULL or misaligned");
+  const int64_t nblk = (n + kBlock - 1) / kBlock;
+  if (nblk > kMaxSelBlocks)
+    return fail(FDAS_ERR_INVALID_ARG, "n = %lld has more than %d blocks of %d bins", (long long)n, kMaxSelBlocks,
+                kBlock);
+  DeviceGuard dg(p->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool fast = !p->direct && p->desc.z_max == 42 && p->desc.hsum_index == FDAS_HSUM_STRETCH;
+  if (!fast) {
+    // other methods and index maps: the whole spectrum (a superset of any selection)
+    st = fdas_convolve(p, d_spectrum, n, d_fop, ld, stream);
+    if (st == FDAS_OK) st = fdas_harmonic_sum(p, d_fop, n, ld, nullptr, d_cands, d_counts, stream);
+    return st;
+  }
+  // lists sized for the whole spectrum: every chunk, every tile, two counts
+  const int V = p->geom.V;
+  const int tcols = harmsum_tile_columns();
+  const int cap_c = (int)((n + V - 1) / V);
+  const int cap_t = (int)((n + tcols - 1) / tcols);
+  const int64_t need = (int64_t)cap_c + cap_t + 2;
+  hipError_t e = hipSuccess;
+  if (need > p->list_cap) {
+    // an earlier call's kernels may still read the old lists
+    if (p->d_lists && (e = hipStreamSynchronize(s)) != hipSuccess) return hip_fail(e, "waiting for the stream");
+    if (p->d_lists) (void)hipFree(p->d_lists);
+    p->d_lists = nullptr;
+    p->list_cap = 0;
+    if ((e = hipMalloc(reinterpret_cast<void**>(&p->d_lists), need * sizeof(int))) != hipSuccess)
+      return hip_fail(e, "allocating the block lists");
+    p->list_cap = need;
+  }
+  const int nh = p->desc.n_harm;
+  int* lists = p->d_lists;
+  e = ps_search_lists(d_logits, threshold, n, (int)nblk, nh, V, tcols, lists, cap_c, cap_t, s);
+  if (e == hipSuccess)
+    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2,
+                             p->rows, p->geom, p->conv_slots, lists, cap_c, s, lists + cap_c + cap_t);
+  if (e == hipSuccess) {
+    // every tile slot gets a workgroup; slots past the selection hold -1 and exit
+    HsWork wk{lists + cap_c, cap_t, p->d_hitrows, p->d_hitrow_count, p->tuning.emit_workgroups};
+    e = launch_harmsum(d_fop, n, ld, p->desc.z_max, nh, p->d_ta, d_cands, p->desc.cand_capacity, d_counts, wk,
+                       FDAS_HSUM_STRETCH, s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "launching the flagged-block search");
+  return ok();
+}
+
 }  // extern "C"

@@ -204,17 +204,20 @@ __global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x
   }
 }
 
-// Listed chunks only: pair q = i * rows + z over chunk_list[0 .. nlist).
+// Listed chunks only: pair q = i * rows + z over chunk_list[0 .. nlist); with
+// d_nlist the list length is read from device memory (written by an earlier
+// kernel on the stream).
 __global__ __launch_bounds__(NT, 2) void k_ols_conv_list(const float2* __restrict__ x, int64_t n,
                                                          float* __restrict__ fop, int64_t ld,
                                                          const float2* __restrict__ H,
                                                          const float2* __restrict__ tw1tab,
                                                          const float2* __restrict__ tw2tab, int rows, int tmax,
-                                                         const int* __restrict__ chunk_list, int nlist, int V,
-                                                         int P) {
+                                                         const int* __restrict__ chunk_list, int nlist,
+                                                         const int* __restrict__ d_nlist, int V, int P) {
   __shared__ float2 buf1[16 * RS];
   __shared__ float2 buf2[16 * RS];
   const int tid = threadIdx.x;
+  if (d_nlist) nlist = *d_nlist;
   float2 tw1[15], tw2[15];
   load_twiddles(tw1tab, tw2tab, tw1, tw2, tid);
   int64_t q, hi;
@@ -277,11 +280,11 @@ hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, c
 
 hipError_t launch_ols_conv_list(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
                                 const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
-                                const int* chunk_list, int nlist, hipStream_t s) {
+                                const int* chunk_list, int nlist, hipStream_t s, const int* d_nlist) {
   if (nlist <= 0) return hipSuccess;
   const unsigned grid = (unsigned)std::min<int64_t>((int64_t)nlist * rows, slots);
   hipLaunchKernelGGL(k_ols_conv_list, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, rows, chunk_list,
-                     nlist, g.V, g.P);
+                     nlist, d_nlist, g.V, g.P);
   return hipGetLastError();
 }
 

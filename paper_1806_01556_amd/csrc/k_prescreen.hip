@@ -359,6 +359,112 @@ __global__ void k_ps_zero(float* __restrict__ p, int n) {
   if (i < n) p[i] = 0.0f;
 }
 
+// Device-side block selection of the pre-screened search (one workgroup):
+//   flagged blocks b (logit > threshold) and their harmonic closure, the
+//   blocks [m b, m (b + 1) - 1] of the multiples m j, m = 2..nh, of their
+//   columns (clipped to the spectrum);
+//   the blocks whose FOP the searched blocks' harmonic sums read (each
+//   searched block and the sources floor(j/k), floor(j/k) + 1 of its 4-column
+//   groups, k = 2..nh);
+//   the overlap-save chunks whose valid outputs touch such a block, and the
+//   harmonic-sum tiles of the searched blocks.
+// lists = [chunk list, cap_c][tile list, cap_t, tail set to -1][n_chunks, n_tiles]
+// The same selection as the host side of fdas_search_blocks with the
+// closure of the flagged blocks as its list.
+constexpr int kSelThreads = 1024;
+constexpr int kPsBlock = PBLK;
+
+__device__ __forceinline__ int64_t min64(int64_t a, int64_t b) { return a < b ? a : b; }
+__device__ __forceinline__ int64_t max64(int64_t a, int64_t b) { return a > b ? a : b; }
+
+// exclusive prefix of v over the workgroup; *total receives the sum
+__device__ __forceinline__ int block_exclusive_scan(int v, int* s_scan, int* total) {
+  const int t = threadIdx.x;
+  s_scan[t] = v;
+  __syncthreads();
+  for (int o = 1; o < kSelThreads; o <<= 1) {
+    const int u = t >= o ? s_scan[t - o] : 0;
+    __syncthreads();
+    s_scan[t] += u;
+    __syncthreads();
+  }
+  const int incl = s_scan[t];
+  *total = s_scan[kSelThreads - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+__global__ __launch_bounds__(kSelThreads) void k_ps_search_lists(const float* __restrict__ logits, float thr,
+                                                                 int64_t n, int nblk, int nh, int V, int tcols,
+                                                                 int* __restrict__ lists, int cap_c, int cap_t) {
+  __shared__ unsigned char s_search[kMaxSelBlocks];
+  __shared__ unsigned char s_need[kMaxSelBlocks];
+  __shared__ int s_scan[kSelThreads];
+  const int t = threadIdx.x;
+  for (int b = t; b < nblk; b += kSelThreads) {
+    s_search[b] = 0;
+    s_need[b] = 0;
+  }
+  __syncthreads();
+  for (int f = t; f < nblk; f += kSelThreads) {
+    if (!(logits[f] > thr)) continue;  // NaN never flags
+    s_search[f] = 1;
+    for (int m = 2; m <= nh; ++m) {
+      const int64_t lo = (int64_t)m * f * kPsBlock;
+      const int64_t hi = min64(n - 1, (int64_t)m * ((int64_t)(f + 1) * kPsBlock - 1) + m - 1);
+      for (int64_t q = lo / kPsBlock; q <= hi / kPsBlock && q < nblk; ++q) s_search[q] = 1;
+    }
+  }
+  __syncthreads();
+  for (int b = t; b < nblk; b += kSelThreads) {
+    if (!s_search[b]) continue;
+    s_need[b] = 1;
+    const int64_t j0 = (int64_t)b * kPsBlock, j1 = min64(n, j0 + kPsBlock) - 1;
+    for (int k = 2; k <= nh; ++k) {
+      const int64_t s0 = (j0 / 4 * 4) / k, s1 = min64(n - 1, ((j1 / 4 * 4 + 3) / k) + 1);
+      for (int64_t q = s0 / kPsBlock; q <= s1 / kPsBlock; ++q) s_need[q] = 1;
+    }
+  }
+  __syncthreads();
+  // chunks, in order
+  const int64_t nchunks = (n + V - 1) / V;
+  int base = 0;
+  for (int64_t c0 = 0; c0 < nchunks; c0 += kSelThreads) {
+    const int64_t c = c0 + t;
+    int flag = 0;
+    if (c < nchunks) {
+      const int64_t a = c * V, z = min64(n, a + V) - 1;
+      for (int64_t q = a / kPsBlock; q <= z / kPsBlock && !flag; ++q) flag = s_need[q];
+    }
+    int tot;
+    const int pos = block_exclusive_scan(flag, s_scan, &tot);
+    if (flag && base + pos < cap_c) lists[base + pos] = (int)c;
+    base += tot;
+  }
+  const int nc = min(base, cap_c);
+  // tiles of the searched blocks, in order; the rest of the tile list is -1
+  const int per = kPsBlock / tcols;
+  const int64_t ntiles = (n + tcols - 1) / tcols;
+  int* tl = lists + cap_c;
+  base = 0;
+  for (int b0 = 0; b0 < nblk; b0 += kSelThreads) {
+    const int b = b0 + t;
+    int cnt = 0;
+    if (b < nblk && s_search[b]) cnt = (int)max64(0, min64(per, ntiles - (int64_t)b * per));
+    int tot;
+    const int pos = block_exclusive_scan(cnt, s_scan, &tot);
+    for (int i = 0; i < cnt; ++i)
+      if (base + pos + i < cap_t) tl[base + pos + i] = b * per + i;
+    base += tot;
+  }
+  const int nt = min(base, cap_t);
+  for (int i = nt + t; i < cap_t; i += kSelThreads) tl[i] = -1;
+  if (t == 0) {
+    lists[cap_c + cap_t] = nc;
+    lists[cap_c + cap_t + 1] = nt;
+  }
+}
+
 }  // namespace
 
 // ---- parameter layout --------------------------------------------------------
@@ -457,6 +563,14 @@ hipError_t ps_round(const PsBuffers& pb, hipStream_t s) {
 hipError_t ps_zero(float* p, int n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_ps_zero, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t ps_search_lists(const float* logits, float thr, int64_t n, int nblk, int nh, int V, int tcols, int* lists,
+                           int cap_c, int cap_t, hipStream_t s) {
+  if (nblk < 1 || nblk > kMaxSelBlocks) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ps_search_lists, dim3(1), dim3(kSelThreads), 0, s, logits, thr, n, nblk, nh, V, tcols, lists,
+                     cap_c, cap_t);
   return hipGetLastError();
 }
 

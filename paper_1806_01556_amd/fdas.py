@@ -33,7 +33,7 @@ EXPORTED = (
     "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped", "fdas_prescreen_param_count",
     "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params", "fdas_prescreen_get_params",
     "fdas_prescreen_features", "fdas_prescreen_forward", "fdas_prescreen_gradient", "fdas_prescreen_train_step",
-    "fdas_search_blocks",
+    "fdas_search_blocks", "fdas_search_flagged",
 )
 
 
@@ -132,12 +132,14 @@ def lib():
     L.fdas_prescreen_gradient.argtypes = [vp, vp, vp, i32, flt, vp, vp, vp, vp]
     L.fdas_prescreen_train_step.argtypes = [vp, vp, vp, i32, flt, flt, vp, vp, vp]
     L.fdas_search_blocks.argtypes = [vp, vp, i64, vp, i64, vp, i32, vp, vp, vp]
+    L.fdas_search_flagged.argtypes = [vp, vp, i64, vp, i64, vp, ctypes.c_float, vp, vp, vp]
     for name in ("fdas_plan_create", "fdas_plan_destroy", "fdas_convolve", "fdas_harmonic_sum",
                  "fdas_candidates", "fdas_template_taps", "fdas_thresholds", "fdas_search_batch",
                  "fdas_candidates_batch", "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped",
                  "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params",
                  "fdas_prescreen_get_params", "fdas_prescreen_features", "fdas_prescreen_forward",
-                 "fdas_prescreen_gradient", "fdas_prescreen_train_step", "fdas_search_blocks"):
+                 "fdas_prescreen_gradient", "fdas_prescreen_train_step", "fdas_search_blocks",
+                 "fdas_search_flagged"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -423,6 +425,15 @@ def search_blocks(plan, spectrum, n, fop, blocks, cands, counts, ld=None, stream
     blocks = np.ascontiguousarray(blocks, dtype=np.int32)
     _check(lib().fdas_search_blocks(plan.handle, _ptr(spectrum), int(n), _ptr(fop), int(ld), blocks.ctypes.data,
                                     blocks.size, _ptr(cands), _ptr(counts), _stream(stream)))
+
+
+def search_flagged(plan, spectrum, n, fop, logits, threshold, cands, counts, ld=None, stream=None):
+    """The restricted search on the blocks whose logit exceeds threshold, plus
+    their harmonic closure, selected on the device (asynchronous)."""
+    if ld is None:
+        ld = fop.shape[1]
+    _check(lib().fdas_search_flagged(plan.handle, _ptr(spectrum), int(n), _ptr(fop), int(ld), _ptr(logits),
+                                     float(threshold), _ptr(cands), _ptr(counts), _stream(stream)))
 
 
 def harmonic_closure(blocks, n, n_harm=8):

@@ -11,6 +11,10 @@
   candidates; with a subset, exactly the plain candidates in those columns
   (bit-identical powers), since each searched column's harmonic sum reads
   convolved columns only.
+* fdas_search_flagged (block selection on the device) returns exactly what
+  fdas_search_blocks returns for the harmonic closure of the flagged blocks,
+  for random logits and ragged lengths; no flagged block gives no
+  candidates, every block the plain search; NaN logits never flag.
 """
 
 import numpy as np
@@ -186,3 +190,43 @@ def test_search_blocks_subset_is_exact_on_its_columns(seed):
     ref = _plain(plan, x, n)
     ref = ref[np.isin(ref["r"] // 4096, blocks)]
     _same(got, ref)
+
+
+def _flagged_search(plan, x, n, logits, thr):
+    fop = torch.full((85, fdas.fop_ld(n)), float("nan"), device=_dev())
+    cands, counts = fdas.alloc_cands(plan, _dev())
+    print(f"search_flagged n={n} thr={thr}", flush=True)
+    fdas.search_flagged(plan, x, n, fop, logits, thr, cands, counts)
+    c, hc = fdas.candidates(plan, cands, counts)
+    return c, hc
+
+
+@pytest.mark.parametrize("n,seed", [(1 << 20, 3), (4096 * 37 + 123, 4), (1 << 18, 5)])
+def test_search_flagged_equals_search_blocks_of_the_closure(n, seed):
+    plan = plan42()
+    spec, _ = synth.make_spectrum(n, 950 + seed, n_random=4, r_range=(500, n * 0.4), snr_range=(8, 20))
+    x = torch.from_numpy(spec).to(_dev())
+    nblk = (n + 4095) // 4096
+    g = torch.Generator().manual_seed(seed)
+    logits = torch.randn(nblk, generator=g).to(_dev())
+    thr = 1.3
+    flagged = np.nonzero(logits.cpu().numpy() > thr)[0]
+    got, _ = _flagged_search(plan, x, n, logits, thr)
+    ref = _blocks_search(plan, x, n, fdas.harmonic_closure(flagged, n))
+    _same(got, ref)
+
+
+def test_search_flagged_none_all_and_nan():
+    plan = plan42()
+    n = 4096 * 50 + 7
+    spec, _ = synth.make_spectrum(n, 961, n_random=3, r_range=(500, n * 0.4), snr_range=(8, 20))
+    x = torch.from_numpy(spec).to(_dev())
+    nblk = (n + 4095) // 4096
+    logits = torch.zeros(nblk, device=_dev())
+    c, hc = _flagged_search(plan, x, n, logits, 1.0)  # nothing flagged
+    assert c.size == 0 and not np.any(hc)
+    c, _ = _flagged_search(plan, x, n, logits, -1.0)  # every block
+    _same(c, _plain(plan, x, n))
+    nan = torch.full((nblk,), float("nan"), device=_dev())
+    c, hc = _flagged_search(plan, x, n, nan, -1e30)
+    assert c.size == 0 and not np.any(hc)
