@@ -279,9 +279,11 @@ def bench_prescreen(args, torch, fdas, synth, dev):
     stats = {name: {"ref": 0, "hit": 0, "pref": 0, "phit": 0, "t": 0.0, "flag": [], "search": []}
              for name, _ in qs}
     t_plain = 0.0
+    xs = []
     for ti in range(T):
         spec, pulsars = synth.make_spectrum(n, 6_000_000 + ti, n_random=1 + ti % 3, r_range=(1e4, 2e6))
         x = torch.from_numpy(spec).to(dev)
+        xs.append(x)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         fdas.convolve(plan, x, fop, n=n)
@@ -311,6 +313,68 @@ def bench_prescreen(args, torch, fdas, synth, dev):
                 if any(abs(r // 4096 - b0) <= 1 for _, _, r in ref):
                     st["pref"] += 1
                     st["phit"] += int(any(abs(r // 4096 - b0) <= 1 for _, _, r in (ref & got)))
+    # the same spectra with two in flight, as in the headline: two plans,
+    # pre-screens and streams; features, inference, device-side block
+    # selection (fdas_search_flagged) and search of spectrum k+1 are queued
+    # before the candidates of spectrum k are read back (DMA), at the default
+    # threshold, against the plain search run the same way
+    thr5 = dict(qs)["val_q5"]
+    theta = ps.get_params()
+    pss = [ps, fdas.Prescreen(max_batch=1024)]
+    pss[1].set_params(theta)
+    plans2 = [plan, fdas.plan_create(n_max=n)]
+    fops2 = [fop, fdas.alloc_fop(plans2[1], n, dev)]
+    bufs2 = [(cands, counts), fdas.alloc_cands(plans2[1], dev)]
+    fes = [fe, torch.empty((nblk, 4096), dtype=torch.float32, device=dev)]
+    lgs = [torch.empty(nblk, dtype=torch.float32, device=dev) for _ in range(2)]
+    strs = [torch.cuda.current_stream(), torch.cuda.Stream()]
+    rb_cap = plan.desc.n_harm * plan.desc.cand_capacity
+
+    def pipe(steps, screened, check=False):
+        got = []
+        for k in range(steps + 1):
+            if k < steps:
+                i, xk = k % 2, xs[k % T]
+                st_ = strs[i]
+                if screened:
+                    pss[i].features(xk, n, nblk, fes[i], stream=st_)
+                    pss[i].forward(fes[i], nblk, lgs[i], stream=st_)
+                    fdas.search_flagged(plans2[i], xk, n, fops2[i], lgs[i], thr5, bufs2[i][0], bufs2[i][1],
+                                        stream=st_)
+                else:
+                    fdas.convolve(plans2[i], xk, fops2[i], n=n, stream=st_)
+                    fdas.harmonic_sum(plans2[i], fops2[i], n, bufs2[i][0], bufs2[i][1], stream=st_)
+            if k >= 1:
+                j = (k - 1) % 2
+                c, _ = fdas.candidates(plans2[j], bufs2[j][0], bufs2[j][1], capacity=rb_cap, stream=strs[j],
+                                       allow_overflow=True, copy=False)
+                if check:
+                    got.append(len(significant(c)))
+        return got
+
+    # untimed pass over the T spectra: the significant cells found
+    sig_pre = pipe(T, True, check=True)
+    sig_plain = pipe(T, False, check=True)
+    torch.cuda.synchronize()
+    reps = 4 * T
+    t0 = time.perf_counter()
+    pipe(reps, True)
+    torch.cuda.synchronize()
+    t_pre2 = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    pipe(reps, False)
+    torch.cuda.synchronize()
+    t_plain2 = time.perf_counter() - t0
+    pipelined = {"steps": reps, "prescreen_spectra_per_s": round(reps / t_pre2, 3),
+                 "plain_spectra_per_s": round(reps / t_plain2, 3),
+                 "speedup_vs_plain": round(t_plain2 / t_pre2, 3),
+                 "significant_cells_prescreen": int(sum(sig_pre)),
+                 "significant_cells_plain": int(sum(sig_plain)),
+                 "note": "default threshold; block selection on the device (fdas_search_flagged), "
+                         "readback of step k while step k+1 runs"}
+    pss[1].destroy()
+    plans2[1].destroy()
+
     points = {}
     for name, th in qs:
         st = stats[name]
@@ -338,6 +402,7 @@ def bench_prescreen(args, torch, fdas, synth, dev):
                    "val_spectra": n_val, "train_n": n_tr, "epochs": args.epochs, "train_steps": steps,
                    "pos_weight": round(pos_weight, 3), "p_label": recipe.get("p_label"), "p_sig": recipe["p_sig"]},
         "plain_spectra_per_s": round(T / t_plain, 3),
+        "pipelined": pipelined,
         "operating_point": "val_q5: flag blocks whose logit exceeds the 5 % quantile of the held-out "
                            "positive blocks' logits",
         "significant_cells": stats["val_q5"]["ref"],

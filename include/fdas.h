@@ -252,7 +252,9 @@ fdas_status fdas_prescreen_destroy(fdas_prescreen* ps);             /* NULL is a
 /* FP32 parameters from / to host memory (set also clears the Adam state).  Synchronise. */
 fdas_status fdas_prescreen_set_params(fdas_prescreen* ps, const float* h_theta);
 fdas_status fdas_prescreen_get_params(fdas_prescreen* ps, float* h_theta);
-/* d_features[i][t] = log(1 + |X[4096 h_blocks[i] + t]|^2) (0 past n), float[nblocks][4096]. */
+/* d_features[i][t] = log(1 + |X[4096 h_blocks[i] + t]|^2) (0 past n), float[nblocks][4096].
+ * h_blocks NULL: blocks 0 .. nblocks-1 (asynchronous); otherwise the list is
+ * uploaded synchronously. */
 fdas_status fdas_prescreen_features(fdas_prescreen* ps, const void* d_spectrum, int64_t n, const int32_t* h_blocks,
                                     int32_t nblocks, float* d_features, void* stream);
 /* d_logits[i] for nblocks feature blocks (asynchronous). */

@@ -140,8 +140,17 @@ fdas_status fdas_prescreen_features(fdas_prescreen* ps, const void* d_spectrum, 
                                     int32_t nblocks, float* d_features, void* stream) {
   fdas_status st = check_batch(ps, nblocks);
   if (st != FDAS_OK) return st;
-  if (!d_spectrum || !d_features || !h_blocks || n < 1) return fail(FDAS_ERR_INVALID_ARG, "bad feature arguments");
+  if (!d_spectrum || !d_features || n < 1) return fail(FDAS_ERR_INVALID_ARG, "bad feature arguments");
   const int64_t nblk = (n + kBlock - 1) / kBlock;
+  if (!h_blocks) {
+    // blocks 0 .. nblocks-1: no list to upload, nothing waits for the host
+    if (nblocks > nblk) return fail(FDAS_ERR_INVALID_ARG, "%d blocks > the spectrum's %lld", nblocks, (long long)nblk);
+    DeviceGuard dg0(ps->device);
+    hipError_t e0 = ps_features(static_cast<const float2*>(d_spectrum), n, nullptr, nblocks, d_features,
+                                static_cast<hipStream_t>(stream));
+    if (e0 != hipSuccess) return hip_fail(e0, "computing pre-screen features");
+    return ok();
+  }
   for (int i = 0; i < nblocks; ++i)
     if (h_blocks[i] < 0 || h_blocks[i] >= nblk) return fail(FDAS_ERR_INVALID_ARG, "block %d outside the spectrum", h_blocks[i]);
   DeviceGuard dg(ps->device);

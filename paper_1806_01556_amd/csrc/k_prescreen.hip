@@ -44,7 +44,7 @@ __global__ void k_ps_features(const float2* __restrict__ x, int64_t n, const int
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)nb * PBLK) return;
   const int b = (int)(i / PBLK), t = (int)(i % PBLK);
-  const int64_t j = (int64_t)blocks[b] * PBLK + t;
+  const int64_t j = (int64_t)(blocks ? blocks[b] : b) * PBLK + t;  // no list: blocks 0 .. nb-1
   float v = 0.0f;
   if (j < n) {
     const float2 c = x[j];

@@ -391,6 +391,11 @@ class Prescreen:
         return out
 
     def features(self, spectrum, n, blocks, out, stream=None):
+        """Features of the listed blocks; an int `blocks` means blocks 0 .. blocks-1 (no host list)."""
+        if isinstance(blocks, (int, np.integer)):
+            _check(lib().fdas_prescreen_features(self.handle, _ptr(spectrum), int(n), None, int(blocks), _ptr(out),
+                                                 _stream(stream)))
+            return
         blocks = np.ascontiguousarray(blocks, dtype=np.int32)
         _check(lib().fdas_prescreen_features(self.handle, _ptr(spectrum), int(n), blocks.ctypes.data, blocks.size,
                                              _ptr(out), _stream(stream)))

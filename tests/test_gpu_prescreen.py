@@ -71,6 +71,13 @@ def test_features_match_numpy():
             seg = p[b * 4096:(b + 1) * 4096]
             ref[i, :seg.size] = np.log1p(seg)
         np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=2e-6, atol=2e-6)
+        # blocks 0 .. 3 without a host list
+        lead = torch.full((4, 4096), -1.0, device=_dev())
+        ps.features(x, n, 4, lead)
+        seq = torch.full((4, 4096), -1.0, device=_dev())
+        ps.features(x, n, np.arange(4), seq)
+        torch.cuda.synchronize()
+        assert torch.equal(lead, seq)
     finally:
         ps.destroy()
 
