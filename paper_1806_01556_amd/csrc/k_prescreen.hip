@@ -64,7 +64,10 @@ __global__ __launch_bounds__(256) void k_ps_conv(const float* __restrict__ x, in
                                                  float* __restrict__ out, unsigned char* __restrict__ arg,
                                                  const float* __restrict__ act_below,
                                                  const unsigned char* __restrict__ arg_below) {
-  __shared__ float xs[CIN][PT + 8];
+  // row u of the tile at word u + u / 32: the 8 threads of a channel read
+  // windows 32 positions apart, which then fall in different banks
+  constexpr int XW = PT + 8 + (PT + 8) / 32 + 1;
+  __shared__ float xs[CIN][XW];
   __shared__ unsigned short ws[PC][CIN][PK];
   const int b = blockIdx.y;
   const int t0 = blockIdx.x * PT;
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(256) void k_ps_conv(const float* __restrict__ x, in
   for (int e = tid; e < CIN * (PT + 8); e += 256) {
     const int i = e / (PT + 8), u = e % (PT + 8);
     const int t = t0 + u - 4;
-    xs[i][u] = (t >= 0 && t < L) ? xb[(size_t)i * L + t] : 0.0f;
+    xs[i][u + u / 32] = (t >= 0 && t < L) ? xb[(size_t)i * L + t] : 0.0f;
   }
   for (int e = tid; e < PC * CIN * PK; e += 256) (&ws[0][0][0])[e] = w[e];
   __syncthreads();
@@ -89,7 +92,7 @@ __global__ __launch_bounds__(256) void k_ps_conv(const float* __restrict__ x, in
 #pragma unroll
     for (int k = 0; k < PK; ++k) wk[k] = bf16_to_f(ws[o][i][k]);
 #pragma unroll
-    for (int u = 0; u < PQ + 8; ++u) xw[u] = xs[i][q0 + u];
+    for (int u = 0; u < PQ + 8; ++u) xw[u] = xs[i][q0 + u + (q0 + u) / 32];
 #pragma unroll
     for (int q = 0; q < PQ; ++q)
 #pragma unroll
@@ -97,23 +100,31 @@ __global__ __launch_bounds__(256) void k_ps_conv(const float* __restrict__ x, in
   }
   if (MODE == 0) {
     if (pool == 4) {
+      // the thread's 8 pooled values are consecutive (32-byte aligned: t0 + q0
+      // is a multiple of 32 and Lp of 8): two 16-byte stores, and the max-pool
+      // positions as one 8-byte store (training only)
       const int Lp = L / 4;
+      float best[PQ / 4];
+      unsigned char ba[PQ / 4];
 #pragma unroll
       for (int p = 0; p < PQ / 4; ++p) {
-        float best = fmaxf(acc[4 * p], 0.0f);
-        int ba = 0;
+        best[p] = fmaxf(acc[4 * p], 0.0f);
+        ba[p] = 0;
 #pragma unroll
         for (int qq = 1; qq < 4; ++qq) {
           const float v = fmaxf(acc[4 * p + qq], 0.0f);
-          if (v > best) {
-            best = v;
-            ba = qq;
+          if (v > best[p]) {
+            best[p] = v;
+            ba[p] = (unsigned char)qq;
           }
         }
-        const int pp = (t0 + q0) / 4 + p;
-        out[((size_t)b * PC + o) * Lp + pp] = best;
-        arg[((size_t)b * PC + o) * Lp + pp] = (unsigned char)ba;
       }
+      static_assert(PQ / 4 == 8, "8 pooled values per thread");
+      const size_t o0 = ((size_t)b * PC + o) * Lp + (t0 + q0) / 4;
+      float4* dst = reinterpret_cast<float4*>(out + o0);
+      dst[0] = make_float4(best[0], best[1], best[2], best[3]);
+      dst[1] = make_float4(best[4], best[5], best[6], best[7]);
+      if (arg) *reinterpret_cast<uint2*>(arg + o0) = *reinterpret_cast<const uint2*>(ba);
     } else {
 #pragma unroll
       for (int q = 0; q < PQ; ++q) out[((size_t)b * PC + o) * L + t0 + q0 + q] = fmaxf(acc[q], 0.0f);
@@ -151,21 +162,32 @@ __global__ __launch_bounds__(256) void k_ps_conv_mfma(const float* __restrict__ 
                                                       float* __restrict__ out) {
   __shared__ uint4 xhi[(PT + 8) * PC / 8];  // [PT + 8][32] bf16
   __shared__ uint4 xlo[(PT + 8) * PC / 8];
+  __shared__ unsigned short ws[PC * PC * PK];  // the layer's weights, [o][i][k]
   const int b = blockIdx.y;
   const int t0 = blockIdx.x * PT;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const float* xb = x + (size_t)b * PC * L;
-  unsigned short* sh = reinterpret_cast<unsigned short*>(xhi);
-  unsigned short* sl = reinterpret_cast<unsigned short*>(xlo);
-  for (int e = tid; e < PC * (PT + 8); e += 256) {
-    const int i = e / (PT + 8), u = e % (PT + 8);
+  // weights: coalesced 16-byte copies (PC * PC * PK shorts = 1152 uint4)
+  for (int e = tid; e < PC * PC * PK / 8; e += 256)
+    reinterpret_cast<uint4*>(ws)[e] = reinterpret_cast<const uint4*>(w)[e];
+  // input tile, position-major: thread (u, c) converts channels 8c .. 8c+7 at
+  // one position and writes one 16-byte word of each of xhi / xlo (consecutive
+  // threads, consecutive words: no bank conflicts)
+  for (int e = tid; e < (PT + 8) * 4; e += 256) {
+    const int c = e & 3, u = e >> 2;
     const int t = t0 + u - 4;
-    const float v = (t >= 0 && t < L) ? xb[(size_t)i * L + t] : 0.0f;
-    const unsigned short h = f_to_bf16(v);
-    sh[u * PC + i] = h;
-    sl[u * PC + i] = f_to_bf16(v - bf16_to_f(h));
+    unsigned short h8[8], l8[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float v = (t >= 0 && t < L) ? xb[(size_t)(8 * c + j) * L + t] : 0.0f;
+      h8[j] = f_to_bf16(v);
+      l8[j] = f_to_bf16(v - bf16_to_f(h8[j]));
+    }
+    xhi[u * 4 + c] = *reinterpret_cast<const uint4*>(h8);
+    xlo[u * 4 + c] = *reinterpret_cast<const uint4*>(l8);
   }
+  __syncthreads();
   // A operands: o-tile ot, step k: lane holds W[16 ot + lane%16][8 (lane/16) + e][k], e < 8
   v8bf A[2][PK];
   const int g = lane >> 4, r = lane & 15;
@@ -175,10 +197,9 @@ __global__ __launch_bounds__(256) void k_ps_conv_mfma(const float* __restrict__ 
     for (int k = 0; k < PK; ++k) {
       unsigned short a8[8];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) a8[e] = w[((size_t)(16 * ot + r) * PC + 8 * g + e) * PK + k];
+      for (int e = 0; e < 8; ++e) a8[e] = ws[((16 * ot + r) * PC + 8 * g + e) * PK + k];
       A[ot][k] = __builtin_bit_cast(v8bf, *reinterpret_cast<uint4*>(a8));
     }
-  __syncthreads();
   const int ntile = min(PT, L - t0) / 16;
   for (int tt = wv; tt < ntile; tt += 4) {
     v4fp acc[2] = {v4fp{0.0f, 0.0f, 0.0f, 0.0f}, v4fp{0.0f, 0.0f, 0.0f, 0.0f}};
@@ -494,7 +515,7 @@ hipError_t ps_forward_backward(const PsBuffers& pb, const float* feats, int nb, 
   // forward; inference runs the 32-channel layers on the matrix cores, training
   // on the vector units (it also records the max-pool positions)
   hipLaunchKernelGGL((k_ps_conv<1, 0>), dim3(PBLK / PT, nb), blk, 0, s, feats, PBLK, w + ps_off_w(0),
-                     w + ps_off_b(0), 4, pb.a1, pb.arg1, nullptr, nullptr);
+                     w + ps_off_b(0), 4, pb.a1, train ? pb.arg1 : nullptr, nullptr, nullptr);
   if (train) {
     hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1024 / PT, nb), blk, 0, s, pb.a1, 1024, w + ps_off_w(1),
                        w + ps_off_b(1), 4, pb.a2, pb.arg2, nullptr, nullptr);
