@@ -45,12 +45,17 @@ hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld,
                            const float2* H, const float2* tw1, const float2* tw2,
                            int rows, const OlsGeom& g, int slots, hipStream_t s);
 
-// Only the listed overlap-save chunks (chunk_list[0 .. nlist), device array).
-// With d_nlist the kernel reads the list length from device memory and nlist
-// is only its upper bound (the grid is sized for it).
+// Only the listed overlap-save chunks (chunk_list[0 .. nlist), device array)
+// and templates (FOP rows) z0 .. z0 + nr - 1.  With d_nlist the kernel reads
+// the list length from device memory and nlist is only its upper bound (the
+// grid is sized for it).
 hipError_t launch_ols_conv_list(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
-                                const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
+                                const float2* tw1, const float2* tw2, int z0, int nr, const OlsGeom& g, int slots,
                                 const int* chunk_list, int nlist, hipStream_t s, const int* d_nlist = nullptr);
+
+// FOP rows the stretched harmonic sums read as sources (k = 2 .. nh) of an
+// 2*Z+1-row plane: [*lo, *hi]; empty (lo > hi) when nh < 2.
+void stretch_source_rows(int Z, int nh, int* lo, int* hi);
 
 // One spectrum of a batch for the convolution queue (device table entry).
 struct ConvTrial {
@@ -202,9 +207,10 @@ hipError_t ps_round(const PsBuffers& pb, hipStream_t s);
 hipError_t ps_zero(float* p, int n, hipStream_t s);
 
 // Device-side block selection of the pre-screened search (one workgroup):
-// from the logits of blocks 0..nblk-1 and a threshold, writes the chunk list
-// (cap_c entries), the tile list (cap_t entries, unused tail -1) and the two
-// counts after them into `lists`.  nblk <= kMaxSelBlocks.
+// from the logits of blocks 0..nblk-1 and a threshold, writes into `lists` the
+// searched-chunk list (cap_c entries), the tile list (cap_t entries, unused
+// tail -1), the source-only chunk list (cap_c entries) and the three counts.
+// nblk <= kMaxSelBlocks.
 constexpr int kMaxSelBlocks = 16384;
 hipError_t ps_search_lists(const float* logits, float thr, int64_t n, int nblk, int nh, int V, int tcols, int* lists,
                            int cap_c, int cap_t, hipStream_t s);

@@ -336,6 +336,22 @@ double erlang_threshold(int k, double p_fa) {
   return t;
 }
 
+void stretch_source_rows(int Z, int nh, int* lo, int* hi) {
+  // source row of row r for harmonic k: trunc((r - Z) / k) + Z (C division)
+  *lo = 0;
+  *hi = -1;
+  for (int k = 2; k <= nh; ++k) {
+    const int a = (0 - Z) / k + Z, b = (2 * Z - Z) / k + Z;
+    if (*hi < *lo) {
+      *lo = a;
+      *hi = b;
+    } else {
+      *lo = std::min(*lo, a);
+      *hi = std::max(*hi, b);
+    }
+  }
+}
+
 // Tile order of the harmonic-sum kernel.  The stretched reads of tile t come
 // from tiles t/k; for k = 2, 4, 8 these are the doubling chain below t.  Tiles
 // are sorted by the fraction of log2(t) (the bits after the leading one,

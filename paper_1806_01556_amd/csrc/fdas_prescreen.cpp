@@ -242,29 +242,37 @@ fdas_status fdas_search_blocks(fdas_plan* p, const void* d_spectrum, int64_t n, 
     if (st == FDAS_OK) st = fdas_harmonic_sum(p, d_fop, n, ld, nullptr, d_cands, d_counts, stream);
     return st;
   }
-  // columns to search, and the columns their harmonic sums read
+  // columns to search (all FOP rows needed there), and the columns their
+  // harmonic sums read as stretched sources (only the source rows needed)
   std::set<int64_t> search(h_blocks, h_blocks + nblocks);
-  std::vector<char> need_col_block(nblk, 0);  // 4096-bin blocks whose FOP must exist
+  std::vector<char> full_block(nblk, 0), src_block(nblk, 0);
   const int nh = p->desc.n_harm;
   for (int64_t b : search) {
     const int64_t j0 = b * kBlock, j1 = std::min<int64_t>(n, j0 + kBlock) - 1;
-    need_col_block[b] = 1;
+    full_block[b] = 1;
     for (int k = 2; k <= nh; ++k) {
       // sources floor(j/k) and the neighbour floor(j/k) + 1 read for 4 columns at once
       const int64_t s0 = (j0 / 4 * 4) / k, s1 = std::min<int64_t>(n - 1, ((j1 / 4 * 4 + 3) / k) + 1);
-      for (int64_t q = s0 / kBlock; q <= s1 / kBlock; ++q) need_col_block[q] = 1;
+      for (int64_t q = s0 / kBlock; q <= s1 / kBlock; ++q) src_block[q] = 1;
     }
   }
-  // overlap-save chunks whose valid outputs touch a needed block
+  // overlap-save chunks whose valid outputs touch a searched block (every
+  // template) or only source blocks (the source rows)
   const int V = p->geom.V;
-  std::vector<int> chunks;
+  std::vector<int> chunks, src_chunks;
   const int64_t nchunks = (n + V - 1) / V;
   for (int64_t c = 0; c < nchunks; ++c) {
     const int64_t a = c * V, z = std::min<int64_t>(n, a + V) - 1;
-    bool any = false;
-    for (int64_t q = a / kBlock; q <= z / kBlock && !any; ++q) any = need_col_block[q] != 0;
-    if (any) chunks.push_back((int)c);
+    bool full = false, src = false;
+    for (int64_t q = a / kBlock; q <= z / kBlock; ++q) {
+      full = full || full_block[q] != 0;
+      src = src || src_block[q] != 0;
+    }
+    if (full) chunks.push_back((int)c);
+    else if (src) src_chunks.push_back((int)c);
   }
+  int r_lo = 0, r_hi = -1;
+  stretch_source_rows(p->desc.z_max, nh, &r_lo, &r_hi);
   // harmonic-sum tiles (1024 columns) of the searched blocks
   std::vector<int> tiles;
   const int tcols = harmsum_tile_columns();
@@ -272,7 +280,7 @@ fdas_status fdas_search_blocks(fdas_plan* p, const void* d_spectrum, int64_t n, 
   for (int64_t b : search)
     for (int64_t t = b * (kBlock / tcols); t < (b + 1) * (kBlock / tcols) && t < ntiles; ++t) tiles.push_back((int)t);
   hipError_t e = hipSuccess;
-  const size_t need = chunks.size() + tiles.size() + 2;
+  const size_t need = chunks.size() + src_chunks.size() + tiles.size() + 2;
   if ((int64_t)need > p->list_cap) {
     if (p->d_lists) (void)hipFree(p->d_lists);
     p->d_lists = nullptr;
@@ -282,6 +290,7 @@ fdas_status fdas_search_blocks(fdas_plan* p, const void* d_spectrum, int64_t n, 
     p->list_cap = (int64_t)need;
   }
   std::vector<int> lists(chunks);
+  lists.insert(lists.end(), src_chunks.begin(), src_chunks.end());
   lists.insert(lists.end(), tiles.begin(), tiles.end());
   // the lists are small and read by this call's kernels only: copy synchronously
   if (!lists.empty() &&
@@ -290,10 +299,14 @@ fdas_status fdas_search_blocks(fdas_plan* p, const void* d_spectrum, int64_t n, 
     return hip_fail(e, "uploading the block lists");
   if (tiles.empty()) e = launch_fill_i32(d_counts, nh, 0, s);  // else the harmonic sum resets them
   if (e == hipSuccess && !chunks.empty())
-    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2,
+    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2, 0,
                              p->rows, p->geom, p->conv_slots, p->d_lists, (int)chunks.size(), s);
+  if (e == hipSuccess && !src_chunks.empty())
+    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2, r_lo,
+                             r_hi - r_lo + 1, p->geom, p->conv_slots, p->d_lists + chunks.size(),
+                             (int)src_chunks.size(), s);
   if (e == hipSuccess && !tiles.empty()) {
-    HsWork wk{p->d_lists + chunks.size(), (int)tiles.size(), p->d_hitrows, p->d_hitrow_count,
+    HsWork wk{p->d_lists + chunks.size() + src_chunks.size(), (int)tiles.size(), p->d_hitrows, p->d_hitrow_count,
               p->tuning.emit_workgroups};
     e = launch_harmsum(d_fop, n, ld, p->desc.z_max, nh, p->d_ta, d_cands, p->desc.cand_capacity, d_counts, wk,
                        FDAS_HSUM_STRETCH, s);
@@ -328,12 +341,13 @@ fdas_status fdas_search_flagged(fdas_plan* p, const void* d_spectrum, int64_t n,
     if (st == FDAS_OK) st = fdas_harmonic_sum(p, d_fop, n, ld, nullptr, d_cands, d_counts, stream);
     return st;
   }
-  // lists sized for the whole spectrum: every chunk, every tile, two counts
+  // lists sized for the whole spectrum: every chunk twice (searched, source
+  // only), every tile, three counts
   const int V = p->geom.V;
   const int tcols = harmsum_tile_columns();
   const int cap_c = (int)((n + V - 1) / V);
   const int cap_t = (int)((n + tcols - 1) / tcols);
-  const int64_t need = (int64_t)cap_c + cap_t + 2;
+  const int64_t need = 2 * (int64_t)cap_c + cap_t + 3;
   hipError_t e = hipSuccess;
   if (need > p->list_cap) {
     // an earlier call's kernels may still read the old lists
@@ -347,10 +361,16 @@ fdas_status fdas_search_flagged(fdas_plan* p, const void* d_spectrum, int64_t n,
   }
   const int nh = p->desc.n_harm;
   int* lists = p->d_lists;
+  int* counts3 = lists + 2 * cap_c + cap_t;  // searched chunks, tiles, source-only chunks
+  int r_lo = 0, r_hi = -1;
+  stretch_source_rows(p->desc.z_max, nh, &r_lo, &r_hi);
   e = ps_search_lists(d_logits, threshold, n, (int)nblk, nh, V, tcols, lists, cap_c, cap_t, s);
   if (e == hipSuccess)
-    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2,
-                             p->rows, p->geom, p->conv_slots, lists, cap_c, s, lists + cap_c + cap_t);
+    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2, 0,
+                             p->rows, p->geom, p->conv_slots, lists, cap_c, s, counts3);
+  if (e == hipSuccess)
+    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2, r_lo,
+                             r_hi - r_lo + 1, p->geom, p->conv_slots, lists + cap_c + cap_t, cap_c, s, counts3 + 2);
   if (e == hipSuccess) {
     // every tile slot gets a workgroup; slots past the selection hold -1 and exit
     HsWork wk{lists + cap_c, cap_t, p->d_hitrows, p->d_hitrow_count, p->tuning.emit_workgroups};

@@ -204,14 +204,14 @@ __global__ __launch_bounds__(NT, 2) void k_ols_conv(const float2* __restrict__ x
   }
 }
 
-// Listed chunks only: pair q = i * rows + z over chunk_list[0 .. nlist); with
-// d_nlist the list length is read from device memory (written by an earlier
-// kernel on the stream).
+// Listed chunks only, templates z0 .. z0 + nr - 1: pair q = i * nr + (z - z0)
+// over chunk_list[0 .. nlist); with d_nlist the list length is read from
+// device memory (written by an earlier kernel on the stream).
 __global__ __launch_bounds__(NT, 2) void k_ols_conv_list(const float2* __restrict__ x, int64_t n,
                                                          float* __restrict__ fop, int64_t ld,
                                                          const float2* __restrict__ H,
                                                          const float2* __restrict__ tw1tab,
-                                                         const float2* __restrict__ tw2tab, int rows, int tmax,
+                                                         const float2* __restrict__ tw2tab, int z0, int nr,
                                                          const int* __restrict__ chunk_list, int nlist,
                                                          const int* __restrict__ d_nlist, int V, int P) {
   __shared__ float2 buf1[16 * RS];
@@ -221,13 +221,13 @@ __global__ __launch_bounds__(NT, 2) void k_ols_conv_list(const float2* __restric
   float2 tw1[15], tw2[15];
   load_twiddles(tw1tab, tw2tab, tw1, tw2, tid);
   int64_t q, hi;
-  pair_range((int64_t)nlist * rows, q, hi);
+  pair_range((int64_t)nlist * nr, q, hi);
   while (q < hi) {
-    const int64_t li = q / rows;
-    const int z_lo = (int)(q - li * rows);
-    const int z_hi = piece_end(q, hi, z_lo, rows, tmax);
-    ols_item(x, n, fop, ld, H, chunk_list[li], z_lo, z_hi, V, P, tw1, tw2, buf1, buf2, tid);
-    q += z_hi - z_lo;
+    const int64_t li = q / nr;
+    const int r_lo = (int)(q - li * nr);
+    const int r_hi = piece_end(q, hi, r_lo, nr, nr);
+    ols_item(x, n, fop, ld, H, chunk_list[li], z0 + r_lo, z0 + r_hi, V, P, tw1, tw2, buf1, buf2, tid);
+    q += r_hi - r_lo;
   }
 }
 
@@ -279,11 +279,11 @@ hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, c
 }
 
 hipError_t launch_ols_conv_list(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
-                                const float2* tw1, const float2* tw2, int rows, const OlsGeom& g, int slots,
+                                const float2* tw1, const float2* tw2, int z0, int nr, const OlsGeom& g, int slots,
                                 const int* chunk_list, int nlist, hipStream_t s, const int* d_nlist) {
-  if (nlist <= 0) return hipSuccess;
-  const unsigned grid = (unsigned)std::min<int64_t>((int64_t)nlist * rows, slots);
-  hipLaunchKernelGGL(k_ols_conv_list, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, rows, rows, chunk_list,
+  if (nlist <= 0 || nr <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((int64_t)nlist * nr, slots);
+  hipLaunchKernelGGL(k_ols_conv_list, dim3(grid), dim3(NT), 0, s, x, n, fop, ld, H, tw1, tw2, z0, nr, chunk_list,
                      nlist, d_nlist, g.V, g.P);
   return hipGetLastError();
 }

@@ -383,13 +383,15 @@ __global__ void k_ps_zero(float* __restrict__ p, int n) {
 // Device-side block selection of the pre-screened search (one workgroup):
 //   flagged blocks b (logit > threshold) and their harmonic closure, the
 //   blocks [m b, m (b + 1) - 1] of the multiples m j, m = 2..nh, of their
-//   columns (clipped to the spectrum);
-//   the blocks whose FOP the searched blocks' harmonic sums read (each
-//   searched block and the sources floor(j/k), floor(j/k) + 1 of its 4-column
-//   groups, k = 2..nh);
-//   the overlap-save chunks whose valid outputs touch such a block, and the
-//   harmonic-sum tiles of the searched blocks.
-// lists = [chunk list, cap_c][tile list, cap_t, tail set to -1][n_chunks, n_tiles]
+//   columns (clipped to the spectrum), are searched;
+//   the blocks the searched blocks' harmonic sums read as stretched sources
+//   (the sources floor(j/k), floor(j/k) + 1 of each 4-column group, k =
+//   2..nh) need only the source rows;
+//   overlap-save chunks whose valid outputs touch a searched block are
+//   convolved for every template, chunks that touch only source blocks for
+//   the source rows; the searched blocks' harmonic-sum tiles are listed.
+// lists = [searched chunks, cap_c][tiles, cap_t, tail -1][source-only chunks,
+//          cap_c][n_searched_chunks, n_tiles, n_source_chunks]
 // The same selection as the host side of fdas_search_blocks with the
 // closure of the flagged blocks as its list.
 constexpr int kSelThreads = 1024;
@@ -419,12 +421,12 @@ __global__ __launch_bounds__(kSelThreads) void k_ps_search_lists(const float* __
                                                                  int64_t n, int nblk, int nh, int V, int tcols,
                                                                  int* __restrict__ lists, int cap_c, int cap_t) {
   __shared__ unsigned char s_search[kMaxSelBlocks];
-  __shared__ unsigned char s_need[kMaxSelBlocks];
+  __shared__ unsigned char s_src[kMaxSelBlocks];
   __shared__ int s_scan[kSelThreads];
   const int t = threadIdx.x;
   for (int b = t; b < nblk; b += kSelThreads) {
     s_search[b] = 0;
-    s_need[b] = 0;
+    s_src[b] = 0;
   }
   __syncthreads();
   for (int f = t; f < nblk; f += kSelThreads) {
@@ -439,30 +441,37 @@ __global__ __launch_bounds__(kSelThreads) void k_ps_search_lists(const float* __
   __syncthreads();
   for (int b = t; b < nblk; b += kSelThreads) {
     if (!s_search[b]) continue;
-    s_need[b] = 1;
     const int64_t j0 = (int64_t)b * kPsBlock, j1 = min64(n, j0 + kPsBlock) - 1;
     for (int k = 2; k <= nh; ++k) {
       const int64_t s0 = (j0 / 4 * 4) / k, s1 = min64(n - 1, ((j1 / 4 * 4 + 3) / k) + 1);
-      for (int64_t q = s0 / kPsBlock; q <= s1 / kPsBlock; ++q) s_need[q] = 1;
+      for (int64_t q = s0 / kPsBlock; q <= s1 / kPsBlock; ++q) s_src[q] = 1;
     }
   }
   __syncthreads();
-  // chunks, in order
+  // chunks, in order: searched (every template) and source-only
   const int64_t nchunks = (n + V - 1) / V;
-  int base = 0;
+  int* sl = lists + cap_c + cap_t;
+  int base = 0, sbase = 0;
   for (int64_t c0 = 0; c0 < nchunks; c0 += kSelThreads) {
     const int64_t c = c0 + t;
-    int flag = 0;
+    int full = 0, src = 0;
     if (c < nchunks) {
       const int64_t a = c * V, z = min64(n, a + V) - 1;
-      for (int64_t q = a / kPsBlock; q <= z / kPsBlock && !flag; ++q) flag = s_need[q];
+      for (int64_t q = a / kPsBlock; q <= z / kPsBlock; ++q) {
+        full |= s_search[q];
+        src |= s_src[q];
+      }
     }
-    int tot;
-    const int pos = block_exclusive_scan(flag, s_scan, &tot);
-    if (flag && base + pos < cap_c) lists[base + pos] = (int)c;
+    const int only_src = src && !full;
+    int tot, stot;
+    const int pos = block_exclusive_scan(full, s_scan, &tot);
+    const int spos = block_exclusive_scan(only_src, s_scan, &stot);
+    if (full && base + pos < cap_c) lists[base + pos] = (int)c;
+    if (only_src && sbase + spos < cap_c) sl[sbase + spos] = (int)c;
     base += tot;
+    sbase += stot;
   }
-  const int nc = min(base, cap_c);
+  const int nc = min(base, cap_c), ns = min(sbase, cap_c);
   // tiles of the searched blocks, in order; the rest of the tile list is -1
   const int per = kPsBlock / tcols;
   const int64_t ntiles = (n + tcols - 1) / tcols;
@@ -481,8 +490,9 @@ __global__ __launch_bounds__(kSelThreads) void k_ps_search_lists(const float* __
   const int nt = min(base, cap_t);
   for (int i = nt + t; i < cap_t; i += kSelThreads) tl[i] = -1;
   if (t == 0) {
-    lists[cap_c + cap_t] = nc;
-    lists[cap_c + cap_t + 1] = nt;
+    lists[2 * cap_c + cap_t] = nc;
+    lists[2 * cap_c + cap_t + 1] = nt;
+    lists[2 * cap_c + cap_t + 2] = ns;
   }
 }
 
