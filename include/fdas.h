@@ -275,8 +275,11 @@ fdas_status fdas_prescreen_train_step(fdas_prescreen* ps, const float* d_feature
  * read, the harmonic sum and compaction on the listed blocks' columns only, so
  * every candidate reported is one fdas_convolve + fdas_harmonic_sum would
  * report, with the same power.  FOP columns outside those chunks are not
- * written.  Plans other than overlap-save / 85 rows / stretch search the whole
- * spectrum.  Asynchronous (the block lists are uploaded synchronously). */
+ * written, and chunks that only hold the stretched sources of the listed
+ * blocks are convolved for the rows the stretched map reads (z = -21..21 of
+ * -42..42) only.  Plans other than overlap-save / 85 rows / stretch search
+ * the whole spectrum.  Asynchronous (the block lists are uploaded
+ * synchronously). */
 fdas_status fdas_search_blocks(fdas_plan* plan, const void* d_spectrum, int64_t n, float* d_fop, int64_t ld,
                                const int32_t* h_blocks, int32_t nblocks, fdas_cand* d_cands, int32_t* d_counts,
                                void* stream);
