@@ -192,11 +192,13 @@ struct PsBuffers {
   float* v;
   unsigned short* wbf;   // BF16 copy used by the kernels
   unsigned short* wflip; // [32][32][9] transposed, flipped kernel of one layer
+  unsigned short* wpack; // layers 1..3 as matrix-core A operands (kPsPackShorts)
   float *a1, *a2, *a3, *r4;               // activations [B][32][1024 / 256 / 64 / 64]
   unsigned char *arg1, *arg2, *arg3;      // max-pool positions
   float *dz1, *dz2, *dz3, *dz4;           // pre-activation gradients [B][32][4096 / 1024 / 256 / 64]
 };
 int ps_param_count();
+constexpr int kPsPackShorts = 3 * 2 * 9 * 64 * 8;
 // features of listed 4096-bin blocks: log(1 + |X|^2)
 hipError_t ps_features(const float2* x, int64_t n, const int* blocks, int nb, float* out, hipStream_t s);
 // forward (logits); with labels also the loss (atomically added, mean) and the gradient into pb.grad

@@ -82,6 +82,7 @@ fdas_status fdas_prescreen_create(int32_t device, int32_t max_batch, fdas_prescr
   if ((e = alloc(ps, &b.theta, np)) != hipSuccess || (e = alloc(ps, &b.grad, np)) != hipSuccess ||
       (e = alloc(ps, &b.m, np)) != hipSuccess || (e = alloc(ps, &b.v, np)) != hipSuccess ||
       (e = alloc(ps, &b.wbf, np)) != hipSuccess || (e = alloc(ps, &b.wflip, C * C * 9)) != hipSuccess ||
+      (e = alloc(ps, &b.wpack, kPsPackShorts)) != hipSuccess ||
       (e = alloc(ps, &b.a1, B * C * 1024)) != hipSuccess || (e = alloc(ps, &b.a2, B * C * 256)) != hipSuccess ||
       (e = alloc(ps, &b.a3, B * C * 64)) != hipSuccess || (e = alloc(ps, &b.r4, B * C * 64)) != hipSuccess ||
       (e = alloc(ps, &b.arg1, B * C * 1024)) != hipSuccess || (e = alloc(ps, &b.arg2, B * C * 256)) != hipSuccess ||

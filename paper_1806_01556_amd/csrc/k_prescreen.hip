@@ -18,6 +18,8 @@
 // summed over a tile of positions and a group of samples in registers before
 // one atomic add per weight and workgroup.
 
+#include <algorithm>
+
 #include "fdas_internal.h"
 
 namespace fdas {
@@ -145,91 +147,222 @@ __global__ __launch_bounds__(256) void k_ps_conv(const float* __restrict__ x, in
   }
 }
 
-// Inference form of a 32 -> 32 channel layer on the matrix cores
-// (v_mfma_f32_16x16x32_bf16): out[o][t] = sum over kappa = 32 k + i of
-// W[o][i][k] x[i][t + k - 4], as a GEMM with M = 32 channels (two 16-row
-// tiles), K = 288 taps x channels (9 steps of 32 channels) and N = positions.
-// The weights are BF16 already; each activation is carried as hi + lo BF16
-// halves, so two products per step keep FP32-level accuracy.  The input tile
-// sits in LDS position-major ([position][channel], hi and lo), so a lane's 8
-// consecutive channels of one position are one 16-byte read.
+// Inference: the whole network of one sample in one workgroup, every
+// activation kept in LDS.  Each layer runs on the matrix cores
+// (v_mfma_f32_16x16x32_bf16) as a GEMM with M = 16 positions per tile,
+// N = 32 output channels (two 16-column tiles) and K = taps x input channels:
+// for the 32 -> 32 channel layers out[t][o] = sum over kappa = 32 k + i of
+// x[i][t + k - 4] W[o][i][k], 9 steps of K = 32.  The weights are BF16
+// already; each activation is carried as hi + lo BF16 halves, so two products
+// per step keep FP32-level accuracy.  Activations sit in LDS position-major
+// ([position][channel], hi and lo), so a lane's 8 consecutive channels of one
+// position are one 16-byte read.  With positions as the M rows a lane's four
+// accumulators are 4 consecutive positions of one channel: the max-pool is
+// in-lane.  Layer 0 works in tiles of 64 pooled outputs that go straight into
+// the layer-1 tile; layer 1 pools into the whole 256-position a2, layer 2 into
+// a3 (64 positions), layer 3 into the per-channel maximum.
 typedef float v4fp __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-__global__ __launch_bounds__(256) void k_ps_conv_mfma(const float* __restrict__ x, int L,
-                                                      const unsigned short* __restrict__ w,
-                                                      const unsigned short* __restrict__ bias, int pool,
-                                                      float* __restrict__ out) {
-  __shared__ uint4 xhi[(PT + 8) * PC / 8];  // [PT + 8][32] bf16
-  __shared__ uint4 xlo[(PT + 8) * PC / 8];
-  __shared__ unsigned short ws[PC * PC * PK];  // the layer's weights, [o][i][k]
-  const int b = blockIdx.y;
-  const int t0 = blockIdx.x * PT;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
-  const float* xb = x + (size_t)b * PC * L;
-  // weights: coalesced 16-byte copies (PC * PC * PK shorts = 1152 uint4)
-  for (int e = tid; e < PC * PC * PK / 8; e += 256)
-    reinterpret_cast<uint4*>(ws)[e] = reinterpret_cast<const uint4*>(w)[e];
-  // input tile, position-major: thread (u, c) converts channels 8c .. 8c+7 at
-  // one position and writes one 16-byte word of each of xhi / xlo (consecutive
-  // threads, consecutive words: no bank conflicts)
-  for (int e = tid; e < (PT + 8) * 4; e += 256) {
-    const int c = e & 3, u = e >> 2;
-    const int t = t0 + u - 4;
-    unsigned short h8[8], l8[8];
+// B operands (weights) of layers 1..3 in lane order: word ((l - 1) * 2 + ot) * PK + k,
+// lane holds W_l[16 ot + lane % 16][8 (lane / 16) + e][k], e < 8
+constexpr int kPackWords = 3 * 2 * PK * 64;
+static_assert(kPackWords * 8 == kPsPackShorts, "packed weight buffer size");
+
+__global__ void k_ps_pack(const unsigned short* __restrict__ w1, const unsigned short* __restrict__ w2,
+                          const unsigned short* __restrict__ w3, uint4* __restrict__ pack) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= kPackWords) return;
+  const int lane = i % 64, k = (i / 64) % PK, ot = (i / (64 * PK)) % 2, l = i / (64 * PK * 2);
+  const unsigned short* w = l == 0 ? w1 : (l == 1 ? w2 : w3);
+  unsigned short a8[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float v = (t >= 0 && t < L) ? xb[(size_t)(8 * c + j) * L + t] : 0.0f;
-      h8[j] = f_to_bf16(v);
-      l8[j] = f_to_bf16(v - bf16_to_f(h8[j]));
-    }
-    xhi[u * 4 + c] = *reinterpret_cast<const uint4*>(h8);
-    xlo[u * 4 + c] = *reinterpret_cast<const uint4*>(l8);
-  }
-  __syncthreads();
-  // A operands: o-tile ot, step k: lane holds W[16 ot + lane%16][8 (lane/16) + e][k], e < 8
-  v8bf A[2][PK];
-  const int g = lane >> 4, r = lane & 15;
+  for (int e = 0; e < 8; ++e) a8[e] = w[((16 * ot + lane % 16) * PC + 8 * (lane / 16) + e) * PK + k];
+  pack[i] = *reinterpret_cast<const uint4*>(a8);
+}
+
+__device__ __forceinline__ void load_w(const uint4* __restrict__ pack, int l, int lane, v8bf (&W)[2][PK]) {
 #pragma unroll
   for (int ot = 0; ot < 2; ++ot)
 #pragma unroll
-    for (int k = 0; k < PK; ++k) {
-      unsigned short a8[8];
+    for (int k = 0; k < PK; ++k) W[ot][k] = __builtin_bit_cast(v8bf, pack[(((l - 1) * 2 + ot) * PK + k) * 64 + lane]);
+}
+
+// 16 positions (LDS rows row0 + r + k, k < 9) x 32 channels; lane (r, g)
+// ends with positions 4 g + v, v < 4, of channel 16 ot + r
+__device__ __forceinline__ void mfma_tile(const uint4* xh, const uint4* xl, int row0, const v8bf (&W)[2][PK], int r,
+                                          int g, v4fp (&acc)[2]) {
+  acc[0] = v4fp{0.0f, 0.0f, 0.0f, 0.0f};
+  acc[1] = v4fp{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-      for (int e = 0; e < 8; ++e) a8[e] = ws[((16 * ot + r) * PC + 8 * g + e) * PK + k];
-      A[ot][k] = __builtin_bit_cast(v8bf, *reinterpret_cast<uint4*>(a8));
+  for (int k = 0; k < PK; ++k) {
+    const int u = row0 + r + k;
+    const v8bf xhi = __builtin_bit_cast(v8bf, xh[u * (PC / 8) + g]);
+    const v8bf xlo = __builtin_bit_cast(v8bf, xl[u * (PC / 8) + g]);
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot) {
+      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xhi, W[ot][k], acc[ot], 0, 0, 0);
+      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xlo, W[ot][k], acc[ot], 0, 0, 0);
     }
-  const int ntile = min(PT, L - t0) / 16;
-  for (int tt = wv; tt < ntile; tt += 4) {
-    v4fp acc[2] = {v4fp{0.0f, 0.0f, 0.0f, 0.0f}, v4fp{0.0f, 0.0f, 0.0f, 0.0f}};
+  }
+}
+
+// max-pool of the lane's 4 positions, bias, ReLU (relu(max + b) equals the
+// maximum of relu(. + b)); channel 16 ot + r of LDS row `row` as hi and lo
+// halves; zeros instead where keep is false
+__device__ __forceinline__ void pool4_store(const v4fp (&acc)[2], const float (&bo)[2], int r, int row, uint4* yh,
+                                            uint4* yl, bool keep = true) {
 #pragma unroll
-    for (int k = 0; k < PK; ++k) {
-      const int u = 16 * tt + r + k;  // LDS row of position t0 + 16 tt + r + k - 4
-      const v8bf bh = __builtin_bit_cast(v8bf, xhi[u * (PC / 8) + g]);
-      const v8bf bl = __builtin_bit_cast(v8bf, xlo[u * (PC / 8) + g]);
+  for (int ot = 0; ot < 2; ++ot) {
+    const float m = fmaxf(fmaxf(acc[ot][0], acc[ot][1]), fmaxf(acc[ot][2], acc[ot][3]));
+    const float y = keep ? fmaxf(m + bo[ot], 0.0f) : 0.0f;
+    const unsigned short h = f_to_bf16(y);
+    reinterpret_cast<unsigned short*>(yh)[row * PC + 16 * ot + r] = h;
+    reinterpret_cast<unsigned short*>(yl)[row * PC + 16 * ot + r] = f_to_bf16(y - bf16_to_f(h));
+  }
+}
+
+__device__ __forceinline__ void load_bias(const unsigned short* __restrict__ bias, int r, float (&bo)[2]) {
+  bo[0] = bf16_to_f(bias[r]);
+  bo[1] = bf16_to_f(bias[16 + r]);
+}
+
+constexpr int T1 = 64;           // layer-0 pooled outputs (layer-1 inputs) per tile
+constexpr int FW = 4 * T1 + 40;  // features behind one tile: 4 (T1 + 8) + 8
+
+__global__ __launch_bounds__(256) void k_ps_infer(const float* __restrict__ feats, const unsigned short* __restrict__ w0,
+                                                  const unsigned short* __restrict__ b0, const uint4* __restrict__ pack,
+                                                  const unsigned short* __restrict__ b1,
+                                                  const unsigned short* __restrict__ b2,
+                                                  const unsigned short* __restrict__ b3,
+                                                  const unsigned short* __restrict__ wf,
+                                                  const unsigned short* __restrict__ bf, float* __restrict__ logits) {
+  __shared__ unsigned short fh[FW], fl[FW];                         // features window, hi and lo
+  __shared__ uint4 xh[(T1 + 8) * PC / 8], xl[(T1 + 8) * PC / 8];  // layer-1 input tile, later a3
+  __shared__ uint4 ah[(256 + 8) * PC / 8], al[(256 + 8) * PC / 8];  // a2, rows 4 .. 259
+  __shared__ float hmax[4][PC];
+  const int b = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int g = lane >> 4, r = lane & 15;
+  const float* f = feats + (size_t)b * PBLK;
+  const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
+  if (tid < 32) {  // zero rows 0..3 and 260..263 of a2
+    const int row = tid < 16 ? tid / 4 : 260 + (tid - 16) / 4;
+    ah[row * 4 + (tid & 3)] = zero4;
+    al[row * 4 + (tid & 3)] = zero4;
+  }
+  // layer 0: K = 32 holds the 9 taps twice (k and 16 + k), against the hi and
+  // the lo half of the features, so one product gives 16 positions x 16
+  // channels at FP32-level accuracy.  Lane (r, g) of the weight operand:
+  // W_0[16 ot + r][8 (g % 2) + e], zero past tap 8.
+  v8bf W0[2];
 #pragma unroll
-      for (int ot = 0; ot < 2; ++ot) {
-        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ot][k], bh, acc[ot], 0, 0, 0);
-        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[ot][k], bl, acc[ot], 0, 0, 0);
+  for (int ot = 0; ot < 2; ++ot) {
+    unsigned short a8[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 8 * (g & 1) + e;
+      a8[e] = k < PK ? w0[(16 * ot + r) * PK + k] : (unsigned short)0;
+    }
+    W0[ot] = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(a8));
+  }
+  float bo0[2];
+  load_bias(b0, r, bo0);
+  v8bf W[2][PK];
+  float bo[2];
+  load_w(pack, 1, lane, W);
+  load_bias(b1, r, bo);
+  // the features of tile j + 1 are loaded while tile j is computed
+  float pf0 = 0.0f, pf1 = 0.0f;
+  auto fetch = [&](int j) {
+    const int t = 4 * T1 * j - 20 + tid;
+    pf0 = (t >= 0 && t < PBLK) ? f[t] : 0.0f;
+    pf1 = (tid + 256 < FW && t + 256 < PBLK) ? f[t + 256] : 0.0f;
+  };
+  fetch(0);
+  for (int j = 0; j < 1024 / T1; ++j) {
+    __syncthreads();  // the previous tile is no longer read
+    // window e holds feature 4 T1 j - 20 + e: tile row u (layer-1 input position
+    // T1 j - 4 + u) pools layer-0 outputs 4 (T1 j - 4 + u) + q, q < 4, whose
+    // taps reach 4 before and 4 after them
+    {
+      unsigned short h = f_to_bf16(pf0);
+      fh[tid] = h;
+      fl[tid] = f_to_bf16(pf0 - bf16_to_f(h));
+      if (tid + 256 < FW) {
+        h = f_to_bf16(pf1);
+        fh[tid + 256] = h;
+        fl[tid + 256] = f_to_bf16(pf1 - bf16_to_f(h));
       }
     }
-    // lane holds channels o = 16 ot + 4 g + v at position t = t0 + 16 tt + r
-    const int t = t0 + 16 * tt + r;
+    if (j + 1 < 1024 / T1) fetch(j + 1);
+    __syncthreads();
+    // layer 0: 18 tiles of 16 outputs; tile tt, row r is layer-0 position
+    // 4 T1 j - 16 + 16 tt + r, whose tap k reads window 16 tt + r + k
+    for (int tt = wv; tt < (T1 + 8) / 4; tt += 4) {
+      const int base = 16 * tt + r;
+      const unsigned short* src = g < 2 ? fh : fl;
+      unsigned short b8[8];
+      if ((g & 1) == 0) {
 #pragma unroll
-    for (int ot = 0; ot < 2; ++ot)
+        for (int e = 0; e < 8; ++e) b8[e] = src[base + e];
+      } else {
+        b8[0] = src[base + 8];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int o = 16 * ot + 4 * g + v;
-        float y = fmaxf(acc[ot][v] + bf16_to_f(bias[o]), 0.0f);
-        if (pool == 4) {
-          y = fmaxf(y, __shfl_xor(y, 1));
-          y = fmaxf(y, __shfl_xor(y, 2));
-          if ((r & 3) == 0) out[((size_t)b * PC + o) * (L / 4) + t / 4] = y;
-        } else {
-          out[((size_t)b * PC + o) * L + t] = y;
-        }
+        for (int e = 1; e < 8; ++e) b8[e] = 0;
       }
+      const v8bf X = __builtin_bit_cast(v8bf, *reinterpret_cast<const uint4*>(b8));
+      v4fp acc[2];
+#pragma unroll
+      for (int ot = 0; ot < 2; ++ot)
+        acc[ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(X, W0[ot], v4fp{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+      const int u = 4 * tt + g;  // pooled row, layer-1 input position T1 j - 4 + u
+      const int pos = T1 * j - 4 + u;
+      pool4_store(acc, bo0, r, u, xh, xl, pos >= 0 && pos < 1024);
+    }
+    __syncthreads();
+    // layer 1: wave wv, positions T1 j + 16 wv + 4 g + v, pooled into a2 row T1 j / 4 + 4 wv + g + 4
+    v4fp acc[2];
+    mfma_tile(xh, xl, 16 * wv, W, r, g, acc);
+    pool4_store(acc, bo, r, T1 * j / 4 + 4 * wv + g + 4, ah, al);
+  }
+  __syncthreads();
+  if (tid < 32) {  // a3 in the tile buffer: zero rows 0..3 and 68..71
+    const int row = tid < 16 ? tid / 4 : 68 + (tid - 16) / 4;
+    xh[row * 4 + (tid & 3)] = zero4;
+    xl[row * 4 + (tid & 3)] = zero4;
+  }
+  // layer 2: 16 tiles of 16 positions, pooled into a3 row 4 tt + g + 4
+  load_w(pack, 2, lane, W);
+  load_bias(b2, r, bo);
+  for (int tt = wv; tt < 16; tt += 4) {
+    v4fp acc[2];
+    mfma_tile(ah, al, 16 * tt, W, r, g, acc);
+    pool4_store(acc, bo, r, 4 * tt + g + 4, xh, xl);
+  }
+  __syncthreads();
+  // layer 3: positions 16 wv + 4 g + v; the maximum over positions, bias, ReLU
+  load_w(pack, 3, lane, W);
+  load_bias(b3, r, bo);
+  {
+    v4fp acc[2];
+    mfma_tile(xh, xl, 16 * wv, W, r, g, acc);
+#pragma unroll
+    for (int ot = 0; ot < 2; ++ot) {
+      float m = fmaxf(fmaxf(acc[ot][0], acc[ot][1]), fmaxf(acc[ot][2], acc[ot][3]));
+      m = fmaxf(m, __shfl_xor(m, 16));
+      m = fmaxf(m, __shfl_xor(m, 32));
+      if (g == 0) hmax[wv][16 * ot + r] = fmaxf(m + bo[ot], 0.0f);
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    float lg = bf16_to_f(bf[0]);
+    for (int c = 0; c < PC; ++c) {
+      const float h = fmaxf(fmaxf(hmax[0][c], hmax[1][c]), fmaxf(hmax[2][c], hmax[3][c]));
+      lg = fmaf(bf16_to_f(wf[c]), h, lg);
+    }
+    logits[b] = lg;
   }
 }
 
@@ -522,28 +655,25 @@ hipError_t ps_forward_backward(const PsBuffers& pb, const float* feats, int nb, 
   const unsigned short* w = pb.wbf;
   const dim3 blk(256);
   const bool train = labels != nullptr;
-  // forward; inference runs the 32-channel layers on the matrix cores, training
-  // on the vector units (it also records the max-pool positions)
-  hipLaunchKernelGGL((k_ps_conv<1, 0>), dim3(PBLK / PT, nb), blk, 0, s, feats, PBLK, w + ps_off_w(0),
-                     w + ps_off_b(0), 4, pb.a1, train ? pb.arg1 : nullptr, nullptr, nullptr);
-  if (train) {
-    hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1024 / PT, nb), blk, 0, s, pb.a1, 1024, w + ps_off_w(1),
-                       w + ps_off_b(1), 4, pb.a2, pb.arg2, nullptr, nullptr);
-    hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1, nb), blk, 0, s, pb.a2, 256, w + ps_off_w(2), w + ps_off_b(2), 4,
-                       pb.a3, pb.arg3, nullptr, nullptr);
-    hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1, nb), blk, 0, s, pb.a3, 64, w + ps_off_w(3), w + ps_off_b(3), 1,
-                       pb.r4, nullptr, nullptr, nullptr);
-  } else {
-    hipLaunchKernelGGL(k_ps_conv_mfma, dim3(1024 / PT, nb), blk, 0, s, pb.a1, 1024, w + ps_off_w(1), w + ps_off_b(1),
-                       4, pb.a2);
-    hipLaunchKernelGGL(k_ps_conv_mfma, dim3(1, nb), blk, 0, s, pb.a2, 256, w + ps_off_w(2), w + ps_off_b(2), 4,
-                       pb.a3);
-    hipLaunchKernelGGL(k_ps_conv_mfma, dim3(1, nb), blk, 0, s, pb.a3, 64, w + ps_off_w(3), w + ps_off_b(3), 1,
-                       pb.r4);
+  if (!train) {
+    // inference: the whole network per sample in one kernel, logits only
+    hipLaunchKernelGGL(k_ps_infer, dim3(nb), blk, 0, s, feats, w + ps_off_w(0), w + ps_off_b(0),
+                       reinterpret_cast<const uint4*>(pb.wpack), w + ps_off_b(1), w + ps_off_b(2), w + ps_off_b(3),
+                       w + ps_off_fc(), w + ps_off_fc() + PC, logits);
+    return hipGetLastError();
   }
+  // training forward on the vector units, recording the activations and the
+  // max-pool positions for the backward pass
+  hipLaunchKernelGGL((k_ps_conv<1, 0>), dim3(PBLK / PT, nb), blk, 0, s, feats, PBLK, w + ps_off_w(0),
+                     w + ps_off_b(0), 4, pb.a1, pb.arg1, nullptr, nullptr);
+  hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1024 / PT, nb), blk, 0, s, pb.a1, 1024, w + ps_off_w(1),
+                     w + ps_off_b(1), 4, pb.a2, pb.arg2, nullptr, nullptr);
+  hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1, nb), blk, 0, s, pb.a2, 256, w + ps_off_w(2), w + ps_off_b(2), 4,
+                     pb.a3, pb.arg3, nullptr, nullptr);
+  hipLaunchKernelGGL((k_ps_conv<PC, 0>), dim3(1, nb), blk, 0, s, pb.a3, 64, w + ps_off_w(3), w + ps_off_b(3), 1,
+                     pb.r4, nullptr, nullptr, nullptr);
   hipLaunchKernelGGL(k_ps_head, dim3(nb), dim3(64), 0, s, pb.r4, w + ps_off_fc(), w + ps_off_fc() + PC, labels,
-                     pos_weight, nb, logits, loss, train ? pb.dz4 : nullptr, pb.grad + ps_off_fc());
-  if (!train) return hipGetLastError();
+                     pos_weight, nb, logits, loss, pb.dz4, pb.grad + ps_off_fc());
   // backward: weight gradients of layer 4, then the data gradient into dz3, ...
   hipLaunchKernelGGL(k_ps_wgrad<PC>, dim3(1, (nb + SG - 1) / SG), blk, 0, s, pb.dz4, pb.a3, 64, nb,
                      pb.grad + ps_off_w(3), pb.grad + ps_off_b(3));
@@ -578,17 +708,25 @@ hipError_t ps_features(const float2* x, int64_t n, const int* blocks, int nb, fl
   return hipGetLastError();
 }
 
+// the inference kernel's A operands follow every change of the BF16 weights
+static hipError_t ps_pack(const PsBuffers& pb, hipStream_t s) {
+  const unsigned short* w = pb.wbf;
+  hipLaunchKernelGGL(k_ps_pack, dim3((kPackWords + 255) / 256), dim3(256), 0, s, w + ps_off_w(1), w + ps_off_w(2),
+                     w + ps_off_w(3), reinterpret_cast<uint4*>(pb.wpack));
+  return hipGetLastError();
+}
+
 hipError_t ps_adam(const PsBuffers& pb, float lr, float b1, float b2, float c1, float c2, float eps, hipStream_t s) {
   const int np = ps_param_count();
   hipLaunchKernelGGL(k_ps_adam, dim3((np + 255) / 256), dim3(256), 0, s, pb.theta, pb.grad, pb.m, pb.v, pb.wbf, np, lr,
                      b1, b2, c1, c2, eps);
-  return hipGetLastError();
+  return ps_pack(pb, s);
 }
 
 hipError_t ps_round(const PsBuffers& pb, hipStream_t s) {
   const int np = ps_param_count();
   hipLaunchKernelGGL(k_ps_round, dim3((np + 255) / 256), dim3(256), 0, s, pb.theta, pb.wbf, np);
-  return hipGetLastError();
+  return ps_pack(pb, s);
 }
 
 hipError_t ps_zero(float* p, int n, hipStream_t s) {

@@ -237,3 +237,26 @@ def test_search_flagged_none_all_and_nan():
     nan = torch.full((nblk,), float("nan"), device=_dev())
     c, hc = _flagged_search(plan, x, n, nan, -1e30)
     assert c.size == 0 and not np.any(hc)
+
+
+def test_inference_over_many_samples_matches_training_forward():
+    """More samples than inference workgroup rows (256): each row walks several."""
+    nb = 300
+    X, y = _blocks(nb, 13)
+    ps = fdas.Prescreen(max_batch=nb)
+    try:
+        ps.set_params(_theta(4))
+        xf = torch.from_numpy(X).to(_dev())
+        yl = torch.from_numpy(y).to(_dev())
+        logits = torch.zeros(nb, device=_dev())
+        loss = torch.zeros(1, device=_dev())
+        grad = torch.zeros(ps.param_count(), device=_dev())
+        ps.gradient(xf, yl, nb, 3.0, logits, loss, grad)
+        l2 = torch.full((nb,), float("nan"), device=_dev())
+        ps.forward(xf, nb, l2)
+        torch.cuda.synchronize()
+        a = logits.cpu().numpy().astype(np.float64)
+        b = l2.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(a - b) <= 1e-4 * (1.0 + np.abs(a))), np.max(np.abs(a - b))
+    finally:
+        ps.destroy()
