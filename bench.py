@@ -266,7 +266,7 @@ def bench_prescreen(args, torch, fdas, synth, dev):
     fop = fdas.alloc_fop(plan, n, dev)
     cands, counts = fdas.alloc_cands(plan, dev)
     tsig = fdas.thresholds(8, recipe["p_sig"])
-    fe = torch.empty((nblk, 4096), dtype=torch.float32, device=dev)
+    lgt = torch.empty(nblk, dtype=torch.float32, device=dev)
 
     def significant(c):
         keep = c["power"] > tsig[c["harm"] - 1]
@@ -295,9 +295,8 @@ def bench_prescreen(args, torch, fdas, synth, dev):
             st = stats[name]
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for s0 in range(0, nblk, ps.max_batch):
-                ps.features(x, n, np.arange(s0, min(nblk, s0 + ps.max_batch)), fe[s0:s0 + ps.max_batch])
-            lg = logits_of(fe, nblk).cpu().numpy()
+            ps.infer(x, n, nblk, lgt)  # features and network in one kernel
+            lg = lgt.cpu().numpy()
             flagged = np.nonzero(lg > th)[0]
             search = fdas.harmonic_closure(flagged, n)
             fdas.search_blocks(plan, x, n, fop, search, cands, counts)
@@ -314,18 +313,17 @@ def bench_prescreen(args, torch, fdas, synth, dev):
                     st["pref"] += 1
                     st["phit"] += int(any(abs(r // 4096 - b0) <= 1 for _, _, r in (ref & got)))
     # the same spectra with two in flight, as in the headline: two plans,
-    # pre-screens and streams; features, inference, device-side block
+    # pre-screens and streams; inference from the spectrum, device-side block
     # selection (fdas_search_flagged) and search of spectrum k+1 are queued
     # before the candidates of spectrum k are read back (DMA), at the default
     # threshold, against the plain search run the same way
     thr5 = dict(qs)["val_q5"]
     theta = ps.get_params()
-    pss = [ps, fdas.Prescreen(max_batch=1024)]
+    pss = [ps, fdas.Prescreen(max_batch=1)]  # inference from the spectrum needs no batch workspace
     pss[1].set_params(theta)
     plans2 = [plan, fdas.plan_create(n_max=n)]
     fops2 = [fop, fdas.alloc_fop(plans2[1], n, dev)]
     bufs2 = [(cands, counts), fdas.alloc_cands(plans2[1], dev)]
-    fes = [fe, torch.empty((nblk, 4096), dtype=torch.float32, device=dev)]
     lgs = [torch.empty(nblk, dtype=torch.float32, device=dev) for _ in range(2)]
     strs = [torch.cuda.current_stream(), torch.cuda.Stream()]
     rb_cap = plan.desc.n_harm * plan.desc.cand_capacity
@@ -337,8 +335,7 @@ def bench_prescreen(args, torch, fdas, synth, dev):
                 i, xk = k % 2, xs[k % T]
                 st_ = strs[i]
                 if screened:
-                    pss[i].features(xk, n, nblk, fes[i], stream=st_)
-                    pss[i].forward(fes[i], nblk, lgs[i], stream=st_)
+                    pss[i].infer(xk, n, nblk, lgs[i], stream=st_)
                     fdas.search_flagged(plans2[i], xk, n, fops2[i], lgs[i], thr5, bufs2[i][0], bufs2[i][1],
                                         stream=st_)
                 else:

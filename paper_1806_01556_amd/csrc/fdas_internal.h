@@ -204,6 +204,8 @@ hipError_t ps_features(const float2* x, int64_t n, const int* blocks, int nb, fl
 // forward (logits); with labels also the loss (atomically added, mean) and the gradient into pb.grad
 hipError_t ps_forward_backward(const PsBuffers& pb, const float* feats, int nb, const float* labels, float pos_weight,
                                float* logits, float* loss, hipStream_t s);
+// logits of blocks 0..nb-1 of an n-bin spectrum, the features computed in the inference kernel
+hipError_t ps_infer_spectrum(const PsBuffers& pb, const float2* x, int64_t n, int nb, float* logits, hipStream_t s);
 hipError_t ps_adam(const PsBuffers& pb, float lr, float b1, float b2, float c1, float c2, float eps, hipStream_t s);
 hipError_t ps_round(const PsBuffers& pb, hipStream_t s);
 hipError_t ps_zero(float* p, int n, hipStream_t s);

@@ -185,6 +185,21 @@ fdas_status fdas_prescreen_forward(fdas_prescreen* ps, const float* d_features, 
   return ok();
 }
 
+fdas_status fdas_prescreen_infer(fdas_prescreen* ps, const void* d_spectrum, int64_t n, int32_t nblocks,
+                                 float* d_logits, void* stream) {
+  if (!ps) return fail(FDAS_ERR_INVALID_ARG, "pre-screen is NULL");
+  if (!d_spectrum || !d_logits) return fail(FDAS_ERR_INVALID_ARG, "NULL buffer");
+  if (n < 1) return fail(FDAS_ERR_INVALID_ARG, "spectrum of %lld bins", (long long)n);
+  const int64_t nblk = (n + kBlock - 1) / kBlock;
+  if (nblocks < 1 || nblocks > nblk)
+    return fail(FDAS_ERR_INVALID_ARG, "nblocks %d outside [1, %lld]", nblocks, (long long)nblk);
+  DeviceGuard dg(ps->device);
+  hipError_t e = ps_infer_spectrum(ps->pb, static_cast<const float2*>(d_spectrum), n, nblocks, d_logits,
+                                   static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "pre-screen inference");
+  return ok();
+}
+
 fdas_status fdas_prescreen_gradient(fdas_prescreen* ps, const float* d_features, const float* d_labels,
                                     int32_t nblocks, float pos_weight, float* d_logits, float* d_loss, float* d_grad,
                                     void* stream) {

@@ -227,24 +227,28 @@ __device__ __forceinline__ void load_bias(const unsigned short* __restrict__ bia
   bo[1] = bf16_to_f(bias[16 + r]);
 }
 
-constexpr int T1 = 64;           // layer-0 pooled outputs (layer-1 inputs) per tile
-constexpr int FW = 4 * T1 + 40;  // features behind one tile: 4 (T1 + 8) + 8
+constexpr int T1 = 128;          // layer-0 pooled outputs (layer-1 inputs) per tile
+constexpr int NW = 8;            // waves per inference workgroup, one 16-position tile each in layer 1
+constexpr int FB = PBLK + 40;    // the block's features with 20 zeros on either side
+static_assert(T1 == 16 * NW, "one layer-1 tile per wave");
 
-__global__ __launch_bounds__(256) void k_ps_infer(const float* __restrict__ feats, const unsigned short* __restrict__ w0,
-                                                  const unsigned short* __restrict__ b0, const uint4* __restrict__ pack,
-                                                  const unsigned short* __restrict__ b1,
-                                                  const unsigned short* __restrict__ b2,
-                                                  const unsigned short* __restrict__ b3,
-                                                  const unsigned short* __restrict__ wf,
-                                                  const unsigned short* __restrict__ bf, float* __restrict__ logits) {
-  __shared__ unsigned short fh[FW], fl[FW];                         // features window, hi and lo
+// SPEC false: features from feats, float[nb][4096]; SPEC true: computed here
+// from bins 4096 b + t of the spectrum (n bins), as k_ps_features computes them.
+// At most 128 VGPRs: two 8-wave workgroups per CU.
+template <bool SPEC>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_ps_infer(
+    const float* __restrict__ feats, const float2* __restrict__ spec, int64_t n, const unsigned short* __restrict__ w0,
+    const unsigned short* __restrict__ b0, const uint4* __restrict__ pack, const unsigned short* __restrict__ b1,
+    const unsigned short* __restrict__ b2, const unsigned short* __restrict__ b3, const unsigned short* __restrict__ wf,
+    const unsigned short* __restrict__ bf, float* __restrict__ logits) {
+  __shared__ unsigned short fh[FB], fl[FB];                         // features, hi and lo
   __shared__ uint4 xh[(T1 + 8) * PC / 8], xl[(T1 + 8) * PC / 8];  // layer-1 input tile, later a3
   __shared__ uint4 ah[(256 + 8) * PC / 8], al[(256 + 8) * PC / 8];  // a2, rows 4 .. 259
   __shared__ float hmax[4][PC];
   const int b = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int g = lane >> 4, r = lane & 15;
-  const float* f = feats + (size_t)b * PBLK;
+  const float* f = SPEC ? nullptr : feats + (size_t)b * PBLK;
   const uint4 zero4 = make_uint4(0u, 0u, 0u, 0u);
   if (tid < 32) {  // zero rows 0..3 and 260..263 of a2
     const int row = tid < 16 ? tid / 4 : 260 + (tid - 16) / 4;
@@ -272,35 +276,40 @@ __global__ __launch_bounds__(256) void k_ps_infer(const float* __restrict__ feat
   float bo[2];
   load_w(pack, 1, lane, W);
   load_bias(b1, r, bo);
-  // the features of tile j + 1 are loaded while tile j is computed
-  float pf0 = 0.0f, pf1 = 0.0f;
-  auto fetch = [&](int j) {
-    const int t = 4 * T1 * j - 20 + tid;
-    pf0 = (t >= 0 && t < PBLK) ? f[t] : 0.0f;
-    pf1 = (tid + 256 < FW && t + 256 < PBLK) ? f[t + 256] : 0.0f;
+  // the whole block's features: word e holds feature e - 20 (zero outside
+  // the block and past the spectrum), every load issued before the first store
+  const int64_t bin0 = (int64_t)b * PBLK;
+  auto feature = [&](int t) {
+    if (t < 0 || t >= PBLK) return 0.0f;
+    if (!SPEC) return f[t];
+    if (bin0 + t >= n) return 0.0f;
+    const float2 c = spec[bin0 + t];
+    return log1pf(c.x * c.x + c.y * c.y);
   };
-  fetch(0);
-  for (int j = 0; j < 1024 / T1; ++j) {
-    __syncthreads();  // the previous tile is no longer read
-    // window e holds feature 4 T1 j - 20 + e: tile row u (layer-1 input position
-    // T1 j - 4 + u) pools layer-0 outputs 4 (T1 j - 4 + u) + q, q < 4, whose
-    // taps reach 4 before and 4 after them
-    {
-      unsigned short h = f_to_bf16(pf0);
-      fh[tid] = h;
-      fl[tid] = f_to_bf16(pf0 - bf16_to_f(h));
-      if (tid + 256 < FW) {
-        h = f_to_bf16(pf1);
-        fh[tid + 256] = h;
-        fl[tid + 256] = f_to_bf16(pf1 - bf16_to_f(h));
+  {
+    constexpr int PER = (FB + 64 * NW - 1) / (64 * NW);
+    float fv[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) fv[i] = feature(tid + 64 * NW * i - 20);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int e = tid + 64 * NW * i;
+      if (e < FB) {
+        const unsigned short h = f_to_bf16(fv[i]);
+        fh[e] = h;
+        fl[e] = f_to_bf16(fv[i] - bf16_to_f(h));
       }
     }
-    if (j + 1 < 1024 / T1) fetch(j + 1);
-    __syncthreads();
-    // layer 0: 18 tiles of 16 outputs; tile tt, row r is layer-0 position
-    // 4 T1 j - 16 + 16 tt + r, whose tap k reads window 16 tt + r + k
-    for (int tt = wv; tt < (T1 + 8) / 4; tt += 4) {
-      const int base = 16 * tt + r;
+  }
+  for (int j = 0; j < 1024 / T1; ++j) {
+    __syncthreads();  // the features are in; the previous tile is no longer read
+    // tile row u is layer-1 input position T1 j - 4 + u; it pools layer-0
+    // outputs 4 (T1 j - 4 + u) + q, q < 4, whose taps reach 4 before and 4 after
+    // layer 0: (T1 + 8) / 4 tiles of 16 outputs; tile tt, row r is layer-0
+    // position 4 T1 j - 16 + 16 tt + r, whose tap k reads feature word
+    // 4 T1 j + 16 tt + r + k
+    for (int tt = wv; tt < (T1 + 8) / 4; tt += NW) {
+      const int base = 4 * T1 * j + 16 * tt + r;
       const unsigned short* src = g < 2 ? fh : fl;
       unsigned short b8[8];
       if ((g & 1) == 0) {
@@ -335,16 +344,17 @@ __global__ __launch_bounds__(256) void k_ps_infer(const float* __restrict__ feat
   // layer 2: 16 tiles of 16 positions, pooled into a3 row 4 tt + g + 4
   load_w(pack, 2, lane, W);
   load_bias(b2, r, bo);
-  for (int tt = wv; tt < 16; tt += 4) {
+  for (int tt = wv; tt < 16; tt += NW) {
     v4fp acc[2];
     mfma_tile(ah, al, 16 * tt, W, r, g, acc);
     pool4_store(acc, bo, r, 4 * tt + g + 4, xh, xl);
   }
   __syncthreads();
-  // layer 3: positions 16 wv + 4 g + v; the maximum over positions, bias, ReLU
-  load_w(pack, 3, lane, W);
-  load_bias(b3, r, bo);
-  {
+  // layer 3 (waves 0..3): positions 16 wv + 4 g + v; the maximum over
+  // positions, bias, ReLU
+  if (wv < 4) {
+    load_w(pack, 3, lane, W);
+    load_bias(b3, r, bo);
     v4fp acc[2];
     mfma_tile(xh, xl, 16 * wv, W, r, g, acc);
 #pragma unroll
@@ -657,7 +667,8 @@ hipError_t ps_forward_backward(const PsBuffers& pb, const float* feats, int nb, 
   const bool train = labels != nullptr;
   if (!train) {
     // inference: the whole network per sample in one kernel, logits only
-    hipLaunchKernelGGL(k_ps_infer, dim3(nb), blk, 0, s, feats, w + ps_off_w(0), w + ps_off_b(0),
+    hipLaunchKernelGGL(k_ps_infer<false>, dim3(nb), dim3(64 * NW), 0, s, feats, nullptr, (int64_t)0, w + ps_off_w(0),
+                       w + ps_off_b(0),
                        reinterpret_cast<const uint4*>(pb.wpack), w + ps_off_b(1), w + ps_off_b(2), w + ps_off_b(3),
                        w + ps_off_fc(), w + ps_off_fc() + PC, logits);
     return hipGetLastError();
@@ -705,6 +716,14 @@ hipError_t ps_features(const float2* x, int64_t n, const int* blocks, int nb, fl
   const int64_t total = (int64_t)nb * PBLK;
   if (total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_ps_features, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, x, n, blocks, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t ps_infer_spectrum(const PsBuffers& pb, const float2* x, int64_t n, int nb, float* logits, hipStream_t s) {
+  const unsigned short* w = pb.wbf;
+  hipLaunchKernelGGL(k_ps_infer<true>, dim3(nb), dim3(64 * NW), 0, s, nullptr, x, n, w + ps_off_w(0), w + ps_off_b(0),
+                     reinterpret_cast<const uint4*>(pb.wpack), w + ps_off_b(1), w + ps_off_b(2), w + ps_off_b(3),
+                     w + ps_off_fc(), w + ps_off_fc() + PC, logits);
   return hipGetLastError();
 }
 

@@ -32,8 +32,8 @@ EXPORTED = (
     "fdas_template_taps", "fdas_thresholds", "fdas_search_batch", "fdas_candidates_batch",
     "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped", "fdas_prescreen_param_count",
     "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params", "fdas_prescreen_get_params",
-    "fdas_prescreen_features", "fdas_prescreen_forward", "fdas_prescreen_gradient", "fdas_prescreen_train_step",
-    "fdas_search_blocks", "fdas_search_flagged",
+    "fdas_prescreen_features", "fdas_prescreen_forward", "fdas_prescreen_infer", "fdas_prescreen_gradient",
+    "fdas_prescreen_train_step", "fdas_search_blocks", "fdas_search_flagged",
 )
 
 
@@ -129,6 +129,7 @@ def lib():
     L.fdas_prescreen_get_params.argtypes = [vp, vp]
     L.fdas_prescreen_features.argtypes = [vp, vp, i64, vp, i32, vp, vp]
     L.fdas_prescreen_forward.argtypes = [vp, vp, i32, vp, vp]
+    L.fdas_prescreen_infer.argtypes = [vp, vp, i64, i32, vp, vp]
     L.fdas_prescreen_gradient.argtypes = [vp, vp, vp, i32, flt, vp, vp, vp, vp]
     L.fdas_prescreen_train_step.argtypes = [vp, vp, vp, i32, flt, flt, vp, vp, vp]
     L.fdas_search_blocks.argtypes = [vp, vp, i64, vp, i64, vp, i32, vp, vp, vp]
@@ -138,7 +139,7 @@ def lib():
                  "fdas_candidates_batch", "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped",
                  "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params",
                  "fdas_prescreen_get_params", "fdas_prescreen_features", "fdas_prescreen_forward",
-                 "fdas_prescreen_gradient", "fdas_prescreen_train_step", "fdas_search_blocks",
+                 "fdas_prescreen_infer", "fdas_prescreen_gradient", "fdas_prescreen_train_step", "fdas_search_blocks",
                  "fdas_search_flagged"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
@@ -402,6 +403,11 @@ class Prescreen:
 
     def forward(self, feats, nb, logits, stream=None):
         _check(lib().fdas_prescreen_forward(self.handle, _ptr(feats), int(nb), _ptr(logits), _stream(stream)))
+
+    def infer(self, spectrum, n, nb, logits, stream=None):
+        """Logits of blocks 0 .. nb-1 straight from the spectrum (features computed in the kernel)."""
+        _check(lib().fdas_prescreen_infer(self.handle, _ptr(spectrum), int(n), int(nb), _ptr(logits),
+                                          _stream(stream)))
 
     def gradient(self, feats, labels, nb, pos_weight, logits, loss, grad=None, stream=None):
         _check(lib().fdas_prescreen_gradient(self.handle, _ptr(feats), _ptr(labels), int(nb), float(pos_weight),

@@ -7,6 +7,9 @@
   accumulate in FP32, so logits agree to ~1e-5 relative and each gradient
   tensor to ~1e-4 of its norm (the bounds below leave a factor of ~10).
 * A few Adam steps on a separable toy set lower the loss.
+* fdas_prescreen_infer (features computed in the inference kernel) gives the
+  logits of fdas_prescreen_features + fdas_prescreen_forward bit for bit, for
+  ragged lengths and for more blocks than the workspace's max_batch.
 * fdas_search_blocks: with every block it returns exactly the plain search's
   candidates; with a subset, exactly the plain candidates in those columns
   (bit-identical powers), since each searched column's harmonic sum reads
@@ -258,5 +261,46 @@ def test_inference_over_many_samples_matches_training_forward():
         a = logits.cpu().numpy().astype(np.float64)
         b = l2.cpu().numpy().astype(np.float64)
         assert np.all(np.abs(a - b) <= 1e-4 * (1.0 + np.abs(a))), np.max(np.abs(a - b))
+    finally:
+        ps.destroy()
+
+
+@pytest.mark.parametrize("n", [4096 * 5 + 1, 4096 * 300, (1 << 20) - 77])
+def test_infer_from_the_spectrum_equals_features_then_forward(n):
+    nblk = (n + 4095) // 4096
+    ps = fdas.Prescreen(max_batch=64)
+    try:
+        ps.set_params(_theta(6))
+        spec, _ = synth.make_spectrum(n, 70 + n % 97, n_random=3, r_range=(100, n * 0.9), snr_range=(8, 30))
+        x = torch.from_numpy(spec).to(_dev())
+        got = torch.full((nblk,), float("nan"), device=_dev())
+        print(f"infer n={n} blocks={nblk}", flush=True)
+        ps.infer(x, n, nblk, got)
+        ref = torch.full((nblk,), float("nan"), device=_dev())
+        fe = torch.empty((64, 4096), device=_dev())
+        for s0 in range(0, nblk, 64):  # the two-step path in batches of max_batch
+            m = min(64, nblk - s0)
+            ps.features(x, n, np.arange(s0, s0 + m), fe[:m])
+            ps.forward(fe[:m], m, ref[s0:s0 + m])
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
+        part = torch.full((nblk,), float("nan"), device=_dev())
+        ps.infer(x, n, max(1, nblk // 2), part)  # a prefix of the blocks
+        torch.cuda.synchronize()
+        k = max(1, nblk // 2)
+        assert torch.equal(part[:k], ref[:k]) and torch.isnan(part[k:]).all()
+    finally:
+        ps.destroy()
+
+
+def test_infer_rejects_blocks_past_the_spectrum():
+    ps = fdas.Prescreen(max_batch=4)
+    try:
+        x = torch.zeros(2 * 4096 + 1, dtype=torch.complex64, device=_dev())
+        out = torch.zeros(8, device=_dev())
+        with pytest.raises(fdas.FdasError):
+            ps.infer(x, 2 * 4096 + 1, 4, out)
+        ps.infer(x, 2 * 4096 + 1, 3, out)
+        torch.cuda.synchronize()
     finally:
         ps.destroy()
