@@ -1,7 +1,8 @@
 // Learned block pre-screen: a 1D convolutional network over the zero-drift
 // power of 4096-bin blocks (not part of the paper's method; a screen that
 // decides which blocks need the full search).  Training and inference
-// kernels, BF16 weights with FP32 accumulation and FP32 activations.
+// kernels, BF16 weights with FP32 accumulation; training keeps FP32
+// activations in global memory, inference (k_ps_infer) keeps them in LDS.
 //
 //   a0[t] = log(1 + |X[t]|^2), t < 4096
 //   a_l = maxpool4(relu(conv(a_{l-1}; W_l, b_l))), l = 1..3  (1->32->32->32 channels)
@@ -10,15 +11,13 @@
 //   conv(x; W, b)[o][t] = b[o] + sum_i sum_{k<9} W[o][i][k] x[i][t + k - 4]  (zero outside)
 //   loss = w y softplus(-logit) + (1 - y) softplus(logit)   (mean over the batch)
 //
-// A conv thread owns 32 consecutive outputs of one channel and walks the
+// Training: a conv thread owns 32 consecutive outputs of one channel and walks the
 // input channels with the 9 weights and a 40-value window of the input in
 // registers (288 FMAs per 49 LDS reads).  The data gradient of a layer is the
 // same loop with the kernel transposed and flipped; its epilogue routes each
 // gradient through the lower layer's max-pool and ReLU.  Weight gradients are
 // summed over a tile of positions and a group of samples in registers before
 // one atomic add per weight and workgroup.
-
-#include <algorithm>
 
 #include "fdas_internal.h"
 
