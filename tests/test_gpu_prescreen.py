@@ -304,3 +304,26 @@ def test_infer_rejects_blocks_past_the_spectrum():
         torch.cuda.synchronize()
     finally:
         ps.destroy()
+
+
+@pytest.mark.parametrize("n", [1, 4095, 4096, 4097])
+def test_infer_tiny_spectra(n):
+    """One or two blocks, mostly zero padding: same logits as features + forward."""
+    nblk = (n + 4095) // 4096
+    rng = np.random.default_rng(n)
+    spec = (rng.standard_normal(n) + 1j * rng.standard_normal(n)).astype(np.complex64) * 3
+    ps = fdas.Prescreen(max_batch=2)
+    try:
+        ps.set_params(_theta(8))
+        x = torch.from_numpy(spec).to(_dev())
+        got = torch.full((nblk,), float("nan"), device=_dev())
+        ps.infer(x, n, nblk, got)
+        fe = torch.empty((nblk, 4096), device=_dev())
+        ps.features(x, n, nblk, fe)
+        ref = torch.full((nblk,), float("nan"), device=_dev())
+        ps.forward(fe, nblk, ref)
+        torch.cuda.synchronize()
+        assert torch.isfinite(got).all()
+        assert torch.equal(got, ref)
+    finally:
+        ps.destroy()
