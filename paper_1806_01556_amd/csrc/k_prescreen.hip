@@ -435,20 +435,35 @@ __global__ __launch_bounds__(64) void k_ps_head(const float* __restrict__ r4, co
 }
 
 // Weight and bias gradients of one layer: dW[o][i][k] += sum_b sum_t dz[b][o][t] x[b][i][t + k - 4].
-// Workgroup = (tile of PT positions, group of SG samples); each thread sums
-// its (o, i) pairs in registers, then one atomic per weight.
-constexpr int SG = 16;
+// Workgroup = (tile of PT positions, group of wgrad_group samples); each thread sums
+// its (o, i) pairs (or, for one input channel, its pair over one of several
+// position segments) in registers, then one atomic per weight.
+// Samples per group: every workgroup adds its partial sums to the same
+// weights, and float atomics on one address serialise in L2, so the
+// one-channel layer (288 weights) takes larger groups.
+template <int CIN>
+constexpr int wgrad_group() {
+  return CIN == 1 ? 16 : 4;
+}
+constexpr int XR = PT + 9;  // x row stride: odd, so the 32 input channels of a wave fall in distinct banks
 template <int CIN>
 __global__ __launch_bounds__(256) void k_ps_wgrad(const float* __restrict__ dz, const float* __restrict__ x, int L,
                                                   int nb, float* __restrict__ gw, float* __restrict__ gb) {
-  __shared__ float xs[CIN][PT + 8];
+  constexpr int SG = wgrad_group<CIN>();
+  __shared__ float xs[CIN][XR];
   __shared__ float ds[PC][PT];
   const int t0 = blockIdx.x * PT;
   const int b0 = blockIdx.y * SG;
   const int tid = threadIdx.x;
-  const int T = min(PT, L - t0);
+  const int T = min(PT, L - t0);  // a multiple of 8: L is 64, 256, 1024 or 4096
   constexpr int PAIRS = PC * CIN;
   constexpr int PPT = (PAIRS + 255) / 256;
+  // fewer pairs than threads (CIN = 1): the threads of a pair split the positions
+  constexpr int NSEG = PAIRS >= 256 ? 1 : 256 / PAIRS;
+  static_assert(NSEG == 1 || PPT == 1, "either several pairs or several segments per thread");
+  const int seg = NSEG == 1 ? 0 : tid / PAIRS;
+  const int TS = NSEG == 1 ? T : ((T + NSEG - 1) / NSEG + 7) / 8 * 8;  // segment length, a multiple of 8
+  const int tb0 = seg * TS, tb1 = min(T, tb0 + TS);
   float acc[PPT][PK];
   float accb = 0.0f;
 #pragma unroll
@@ -470,26 +485,48 @@ __global__ __launch_bounds__(256) void k_ps_wgrad(const float* __restrict__ dz, 
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
-      const int pr = tid + 256 * u;
+      const int pr = NSEG == 1 ? tid + 256 * u : tid % PAIRS;
       if (pr < PAIRS) {
         const int o = pr / CIN, i = pr % CIN;
-        for (int t = 0; t < T; ++t) {
-          const float d = ds[o][t];
+        // 8 positions at a time from a 16-value window in registers (the sum
+        // over t of each tap still runs in t order)
+        for (int tb = tb0; tb < tb1; tb += 8) {
+          float dv[8], xw[16];
 #pragma unroll
-          for (int k = 0; k < PK; ++k) acc[u][k] = fmaf(d, xs[i][t + k], acc[u][k]);
+          for (int q = 0; q < 8; ++q) dv[q] = ds[o][tb + q];
+#pragma unroll
+          for (int e = 0; e < 16; ++e) xw[e] = xs[i][tb + e];
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+#pragma unroll
+            for (int k = 0; k < PK; ++k) acc[u][k] = fmaf(dv[q], xw[q + k], acc[u][k]);
         }
       }
     }
     if (tid < PC)
       for (int t = 0; t < T; ++t) accb += ds[tid][t];
   }
+  if (NSEG > 1) {
+    // the segments' partial sums of each weight meet in LDS: one atomic per weight
+    __shared__ float red[NSEG > 1 ? NSEG * PAIRS * PK : 1];
+    __syncthreads();
 #pragma unroll
-  for (int u = 0; u < PPT; ++u) {
-    const int pr = tid + 256 * u;
-    if (pr < PAIRS) {
-      const int o = pr / CIN, i = pr % CIN;
+    for (int k = 0; k < PK; ++k) red[(seg * PAIRS + tid % PAIRS) * PK + k] = acc[0][k];
+    __syncthreads();
+    for (int w = tid; w < PAIRS * PK; w += 256) {
+      float v = 0.0f;
+      for (int q = 0; q < NSEG; ++q) v += red[q * PAIRS * PK + w];
+      atomicAdd(&gw[w], v);  // w = (o * CIN + i) * PK + k with CIN = 1
+    }
+  } else {
 #pragma unroll
-      for (int k = 0; k < PK; ++k) atomicAdd(&gw[((size_t)o * CIN + i) * PK + k], acc[u][k]);
+    for (int u = 0; u < PPT; ++u) {
+      const int pr = tid + 256 * u;
+      if (pr < PAIRS) {
+        const int o = pr / CIN, i = pr % CIN;
+#pragma unroll
+        for (int k = 0; k < PK; ++k) atomicAdd(&gw[((size_t)o * CIN + i) * PK + k], acc[u][k]);
+      }
     }
   }
   if (tid < PC) atomicAdd(&gb[tid], accb);
@@ -685,8 +722,10 @@ hipError_t ps_forward_backward(const PsBuffers& pb, const float* feats, int nb, 
   hipLaunchKernelGGL(k_ps_head, dim3(nb), dim3(64), 0, s, pb.r4, w + ps_off_fc(), w + ps_off_fc() + PC, labels,
                      pos_weight, nb, logits, loss, pb.dz4, pb.grad + ps_off_fc());
   // backward: weight gradients of layer 4, then the data gradient into dz3, ...
-  hipLaunchKernelGGL(k_ps_wgrad<PC>, dim3(1, (nb + SG - 1) / SG), blk, 0, s, pb.dz4, pb.a3, 64, nb,
-                     pb.grad + ps_off_w(3), pb.grad + ps_off_b(3));
+  const unsigned g1 = (unsigned)((nb + wgrad_group<1>() - 1) / wgrad_group<1>());
+  const unsigned g32 = (unsigned)((nb + wgrad_group<PC>() - 1) / wgrad_group<PC>());
+  hipLaunchKernelGGL(k_ps_wgrad<PC>, dim3(1, g32), blk, 0, s, pb.dz4, pb.a3, 64, nb, pb.grad + ps_off_w(3),
+                     pb.grad + ps_off_b(3));
   const float* dz_above = pb.dz4;
   float* dz_below[3] = {pb.dz1, pb.dz2, pb.dz3};
   const float* act[3] = {pb.a1, pb.a2, pb.a3};
@@ -701,11 +740,11 @@ hipError_t ps_forward_backward(const PsBuffers& pb, const float* feats, int nb, 
                        dz_below[l - 1], nullptr, act[l - 1], args[l - 1]);
     // weight gradients of layer l (input x_{l-1}, output gradient dz_below[l-1] at length 4L)
     if (l - 1 == 0)
-      hipLaunchKernelGGL(k_ps_wgrad<1>, dim3(4 * L / PT, (nb + SG - 1) / SG), blk, 0, s, dz_below[0], xin[0], 4 * L,
-                         nb, pb.grad + ps_off_w(0), pb.grad + ps_off_b(0));
+      hipLaunchKernelGGL(k_ps_wgrad<1>, dim3(4 * L / PT, g1), blk, 0, s, dz_below[0], xin[0], 4 * L, nb,
+                         pb.grad + ps_off_w(0), pb.grad + ps_off_b(0));
     else
-      hipLaunchKernelGGL(k_ps_wgrad<PC>, dim3(4 * L / PT, (nb + SG - 1) / SG), blk, 0, s, dz_below[l - 1],
-                         xin[l - 1], 4 * L, nb, pb.grad + ps_off_w(l - 1), pb.grad + ps_off_b(l - 1));
+      hipLaunchKernelGGL(k_ps_wgrad<PC>, dim3(4 * L / PT, g32), blk, 0, s, dz_below[l - 1], xin[l - 1], 4 * L, nb,
+                         pb.grad + ps_off_w(l - 1), pb.grad + ps_off_b(l - 1));
     dz_above = dz_below[l - 1];
   }
   return hipGetLastError();
