@@ -261,9 +261,10 @@ fdas_status fdas_prescreen_features(fdas_prescreen* ps, const void* d_spectrum, 
 fdas_status fdas_prescreen_forward(fdas_prescreen* ps, const float* d_features, int32_t nblocks, float* d_logits,
                                    void* stream);
 /* d_logits[b] for blocks b = 0 .. nblocks-1 of the spectrum (n complex FP32
- * bins on the device), nblocks <= ceil(n / 4096): fdas_prescreen_features
- * followed by fdas_prescreen_forward in one kernel, with no features buffer
- * and no limit from max_batch; the same logits bit for bit.  Asynchronous. */
+ * bins on the device, 8-byte aligned), nblocks <= ceil(n / 4096):
+ * fdas_prescreen_features followed by fdas_prescreen_forward in one kernel,
+ * with no features buffer and no limit from max_batch; the same logits bit
+ * for bit.  Asynchronous. */
 fdas_status fdas_prescreen_infer(fdas_prescreen* ps, const void* d_spectrum, int64_t n, int32_t nblocks,
                                  float* d_logits, void* stream);
 /* Logits, mean loss (d_loss[0]) and, if d_grad != NULL, the mean gradient (float[param_count]). */

@@ -188,7 +188,10 @@ fdas_status fdas_prescreen_forward(fdas_prescreen* ps, const float* d_features, 
 fdas_status fdas_prescreen_infer(fdas_prescreen* ps, const void* d_spectrum, int64_t n, int32_t nblocks,
                                  float* d_logits, void* stream) {
   if (!ps) return fail(FDAS_ERR_INVALID_ARG, "pre-screen is NULL");
-  if (!d_spectrum || !d_logits) return fail(FDAS_ERR_INVALID_ARG, "NULL buffer");
+  if (!d_spectrum || reinterpret_cast<uintptr_t>(d_spectrum) % 8 != 0)
+    return fail(FDAS_ERR_INVALID_ARG, "spectrum pointer is NULL or not 8-byte aligned");
+  if (!d_logits || reinterpret_cast<uintptr_t>(d_logits) % 4 != 0)
+    return fail(FDAS_ERR_INVALID_ARG, "logits pointer is NULL or misaligned");
   if (n < 1) return fail(FDAS_ERR_INVALID_ARG, "spectrum of %lld bins", (long long)n);
   const int64_t nblk = (n + kBlock - 1) / kBlock;
   if (nblocks < 1 || nblocks > nblk)

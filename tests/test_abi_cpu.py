@@ -89,6 +89,7 @@ def test_bad_arguments_rejected_before_device(L):
     assert L.fdas_thresholds(9, 1e-6, None) == fdas.ERR_INVALID_ARG
     assert L.fdas_search_flagged(None, 16, 4, 16, 4, 16, 0.0, 16, 16, None) == fdas.ERR_INVALID_ARG
     assert L.fdas_prescreen_infer(None, 16, 4096, 1, 16, None) == fdas.ERR_INVALID_ARG
+    assert "NULL" in fdas.last_error()
 
 
 @pytest.mark.skipif(_gpu_present(), reason="checks the no-GPU path")
