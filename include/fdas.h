@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define FDAS_ABI_VERSION 1
+#define FDAS_ABI_VERSION 2
 
 typedef enum {
   FDAS_OK = 0,
@@ -57,46 +57,47 @@ typedef enum {
 } fdas_status;
 
 /* FT-convolution method (Section 2.1). */
-enum {
-  FDAS_CONV_AUTO = 0,     /* the faster of the two on this GPU (overlap-save) */
-  FDAS_CONV_OLS_FFT = 1,  /* overlap-save FFT correlation (Section 2.1.2, eq. (2)) */
-  FDAS_CONV_DIRECT = 2    /* direct complex FIR sum on the matrix cores (eq. (1)) */
-};
+typedef enum {
+  FDAS_CONV_AUTO = 0,        /* the faster of the two on this GPU (overlap-save) */
+  FDAS_CONV_OLS_FFT = 1,     /* overlap-save FFT correlation (Section 2.1.2, eq. (2)) */
+  FDAS_CONV_DIRECT_MFMA = 2  /* direct complex FIR sum on the matrix cores (eq. (1)) */
+} fdas_conv_method;
 
 /* Arithmetic of the direct method (the overlap-save method is always FP32).
  * The split forms carry every operand value v as hi = round16(v) and
  * lo = round16(v - hi) and each product as hi*hi + hi*lo + lo*hi on the 16-bit
  * matrix cores with FP32 accumulation (FP16 operands are scaled by exact
  * powers of two per workgroup strip and per template tile). */
-enum {
+typedef enum {
   FDAS_PREC_FP32 = 0,
   FDAS_PREC_SPLIT_FP16 = 1,
   FDAS_PREC_SPLIT_BF16 = 2
-};
+} fdas_precision;
 
 /* Harmonic index map used by fdas_harmonic_sum.  Algorithm 1 names a
  * stretch() it does not define; STRETCH is the literal reading used by
  * default, the other two follow the physics of a signal whose m-th harmonic
  * sits at (m z, m r). */
-enum {
+typedef enum {
   FDAS_HSUM_STRETCH = 0,     /* HP_k = HP_{k-1} + FOP(trunc(i/k), floor(j/k)) */
   FDAS_HSUM_FUNDAMENTAL = 1, /* HP_k = HP_{k-1} + FOP(k i, k j), 0 outside the plane */
   FDAS_HSUM_HIGHEST = 2      /* HP_k = sum_{m<=k} FOP(rho(m i, k), rho(m j, k)), rho = nearest,
                                 halves away from zero; not cumulative */
-};
+} fdas_hsum_index;
 
 typedef struct {
   int32_t struct_size;   /* sizeof(fdas_plan_desc); guards ABI drift */
+  int64_t n_max;         /* largest spectrum length the plan accepts; 1 .. 2^30, and
+                            (2*z_max+1) * n_max < 2^31 so that per-plane counts stay exact */
   int32_t z_max;         /* templates z = -z_max..z_max (row = z + z_max); 0..64, default 42 */
-  int64_t n_max;         /* largest spectrum length the plan accepts; >= 1 */
   int32_t n_harm;        /* harmonic planes N_hp, 1..8, default 8 */
-  int32_t cand_capacity; /* candidates stored per plane on the device, >= 1 */
   double  p_fa;          /* per-cell false-alarm probability of the default TA, (0, 1) */
-  int32_t top_k;         /* fdas_candidates keeps this many per plane (0 = all; 200 = Table 1) */
-  int32_t method;        /* FDAS_CONV_* */
-  int32_t precision;     /* FDAS_PREC_* */
-  int32_t hsum_index;    /* FDAS_HSUM_* */
-  int32_t ols_chunk;     /* overlap-save FFT length; 0 = default (4096); only 4096 is built */
+  int32_t cand_capacity; /* candidates stored per plane on the device, 1 .. 2^22 */
+  int32_t top_k;         /* readback keeps this many per plane (0 = all; 200 = Table 1) */
+  fdas_conv_method method;
+  fdas_precision precision;
+  fdas_hsum_index hsum_index;
+  int32_t ols_chunk;     /* overlap-save FFT length C: 0 = default (4096); only 4096 is built */
   int32_t device;        /* HIP device ordinal */
 } fdas_plan_desc;
 
@@ -157,7 +158,9 @@ fdas_status fdas_harmonic_sum(fdas_plan* plan, const float* d_fop, int64_t n, in
  * by (harm, z, r) and write at most h_capacity records to h_out.  With
  * top_k > 0 each plane keeps its top_k highest powers (ties: lower z, then
  * lower r, first) before ordering.  *h_n receives the number written.
- * h_counts (optional, int32[n_harm]) receives the device counts.
+ * h_counts (optional, int32[n_harm]; NULL to skip) receives the device counts,
+ * the true per-plane totals that tell a caller how much an overflowed list
+ * lost; they are read in the same wait as the records.
  * Returns FDAS_ERR_CAPACITY if a device list overflowed or h_capacity was too
  * small; the records returned are then still ordered but incomplete. */
 fdas_status fdas_candidates(fdas_plan* plan, const fdas_cand* d_cands, const int32_t* d_counts,
@@ -294,16 +297,36 @@ fdas_status fdas_search_blocks(fdas_plan* plan, const void* d_spectrum, int64_t 
 /* The same restricted search with the block selection on the device, so
  * nothing waits for the host between the pre-screen and the search: blocks b
  * with d_logits[b] > threshold (d_logits: float[ceil(n/4096)] on the device,
- * e.g. written by fdas_prescreen_forward over blocks 0, 1, ...; NaN never
- * flags) and their harmonic closure -- the blocks [m b, m (b + 1) - 1],
- * m = 2..n_harm, holding the multiples m j of their columns -- are searched
- * exactly as fdas_search_blocks searches that block list (identical
- * candidates and powers).  n <= 16384 * 4096 bins.  The plan keeps device
- * lists sized for the spectrum.  Plans other than overlap-save / 85 rows /
- * stretch search the whole spectrum.  Asynchronous on stream. */
+ * e.g. written by fdas_prescreen_infer over blocks 0, 1, ...) and their
+ * harmonic closure (as fdas_block_closure) are searched exactly as
+ * fdas_search_blocks searches that block list (identical candidates and
+ * powers).
+ * Fallback to the plain search: when the screen is disabled (d_logits NULL),
+ * when any logit is not finite (a diverged or broken model) or when the
+ * threshold is NaN, every block is searched, which returns exactly what
+ * fdas_convolve + fdas_harmonic_sum return.
+ * n <= 16384 * 4096 bins.  The plan keeps device lists sized for the
+ * spectrum.  Plans other than overlap-save / 85 rows / stretch search the
+ * whole spectrum.  Asynchronous on stream. */
 fdas_status fdas_search_flagged(fdas_plan* plan, const void* d_spectrum, int64_t n, float* d_fop, int64_t ld,
                                 const float* d_logits, float threshold, fdas_cand* d_cands, int32_t* d_counts,
                                 void* stream);
+
+/* Harmonic closure of a block list under the stretched index map (host only):
+ * the listed 4096-bin blocks plus, for every listed block b and m = 2..n_harm,
+ * the blocks holding columns m*j .. m*j + m - 1 of its columns j (a signal at
+ * column j raises the harmonic sums there), clipped to a spectrum of n bins.
+ * h_out receives the distinct blocks in increasing order (*n_out of them;
+ * at most ceil(n / 4096)).  Returns FDAS_ERR_CAPACITY, with *n_out the size
+ * needed, if capacity is too small. */
+fdas_status fdas_block_closure(int64_t n, int32_t n_harm, const int32_t* h_blocks, int32_t nblocks,
+                               int32_t* h_out, int32_t capacity, int32_t* n_out);
+
+/* Initial network parameters (host only): He-uniform convolution weights
+ * (bound sqrt(6 / fan_in)), head weights uniform in +-1/sqrt(32), zero biases,
+ * drawn from a splitmix64 stream seeded with `seed`, in the flat order of
+ * fdas_prescreen_param_count.  h_theta: float[fdas_prescreen_param_count()]. */
+fdas_status fdas_prescreen_init_params(uint64_t seed, float* h_theta);
 
 /* Thread-local description of the last error of this thread ("" if none). */
 const char* fdas_last_error(void);

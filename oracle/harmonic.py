@@ -68,7 +68,7 @@ def stretch_plane(plane, k, cols=None):
     z_max = (plane.shape[0] - 1) // 2
     rows = stretch_rows(k, z_max)
     src = stretch_cols(k, plane.shape[1], cols)
-    return plane[rows][:, src]
+    return plane[np.ix_(rows, src)]
 
 
 def harmonic_planes(plane, n_harm=8, cols=None, index="stretch"):
@@ -198,3 +198,38 @@ def guard_cells(plane, n_harm=8, ta=None, p_fa=1e-6, rel=1e-4, cols=None, index=
         out.update((k, int(r) - z_max, int(colidx[c])) for r, c in zip(rows, cc))
     return out
 
+
+def candidates_and_guard(plane, n_harm=8, ta=None, p_fa=1e-6, rel=1e-4, cols=None, wide=None):
+    """candidates(plane, ...) and guard_cells(plane, ...) of an FP64 plane in
+    one pass over its harmonic planes (the same definitions, each plane
+    formed once): (CAND_DTYPE array in (k, i, j) order, set of (k, z, r)).
+
+    With ``wide`` a third element is returned: per plane, the number of cells
+    with |HP_k - TA(k, i)| <= wide * TA(k, i), the population of a wider band
+    from which the density of harmonic sums around the threshold is read."""
+    plane = np.asarray(plane, dtype=np.float64)
+    z_max = (plane.shape[0] - 1) // 2
+    if ta is None:
+        ta = threshold_array(n_harm, z_max, p_fa)
+    ta = np.asarray(ta, dtype=np.float64)
+    colidx = np.arange(plane.shape[1], dtype=np.int64) if cols is None else np.asarray(cols, dtype=np.int64)
+    out, guard, wide_counts = [], set(), []
+    for k, hp in harmonic_planes(plane, n_harm, cols):
+        t = ta[k - 1][:, None]
+        rows, cc = np.nonzero(hp > t)
+        rec = np.empty(rows.size, dtype=CAND_DTYPE)
+        rec["harm"] = k
+        rec["z"] = rows - z_max
+        rec["r"] = colidx[cc]
+        rec["power"] = hp[rows, cc]
+        out.append(rec)
+        dist = np.abs(hp - t)
+        grows, gcc = np.nonzero(dist <= rel * t)
+        guard.update((k, int(r) - z_max, int(colidx[c])) for r, c in zip(grows, gcc))
+        if wide is not None:
+            wide_counts.append(int(np.count_nonzero(dist <= wide * t)))
+    allc = np.concatenate(out) if out else np.empty(0, dtype=CAND_DTYPE)
+    order = np.lexsort((allc["r"], allc["z"], allc["harm"]))
+    if wide is None:
+        return allc[order], guard
+    return allc[order], guard, np.array(wide_counts, dtype=np.int64)

@@ -181,17 +181,20 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   if (desc->z_max < 0 || desc->z_max > 64) return fail(FDAS_ERR_INVALID_ARG, "z_max = %d outside [0, 64]", (int)desc->z_max);
   if (desc->n_max < 1 || desc->n_max > ((int64_t)1 << 30))
     return fail(FDAS_ERR_INVALID_ARG, "n_max = %lld outside [1, 2^30]", (long long)desc->n_max);
+  if ((int64_t)(2 * desc->z_max + 1) * desc->n_max > (int64_t)INT32_MAX)
+    return fail(FDAS_ERR_INVALID_ARG, "(2*z_max+1) * n_max = %lld: per-plane candidate counts must stay below 2^31",
+                (long long)(2 * desc->z_max + 1) * (long long)desc->n_max);
   if (desc->n_harm < 1 || desc->n_harm > 8) return fail(FDAS_ERR_INVALID_ARG, "n_harm = %d outside [1, 8]", (int)desc->n_harm);
   if (desc->cand_capacity < 1 || desc->cand_capacity > (1 << 22))
     return fail(FDAS_ERR_INVALID_ARG, "cand_capacity = %d outside [1, 2^22]", (int)desc->cand_capacity);
   if (!(desc->p_fa > 0.0 && desc->p_fa < 1.0)) return fail(FDAS_ERR_INVALID_ARG, "p_fa must lie in (0, 1)");
   if (desc->top_k < 0) return fail(FDAS_ERR_INVALID_ARG, "top_k < 0");
-  if (desc->method != FDAS_CONV_AUTO && desc->method != FDAS_CONV_OLS_FFT && desc->method != FDAS_CONV_DIRECT)
+  if (desc->method != FDAS_CONV_AUTO && desc->method != FDAS_CONV_OLS_FFT && desc->method != FDAS_CONV_DIRECT_MFMA)
     return fail(FDAS_ERR_INVALID_ARG, "unknown method %d", (int)desc->method);
   if (desc->precision != FDAS_PREC_FP32 && desc->precision != FDAS_PREC_SPLIT_FP16 &&
       desc->precision != FDAS_PREC_SPLIT_BF16)
     return fail(FDAS_ERR_INVALID_ARG, "unknown precision %d", (int)desc->precision);
-  if (desc->precision != FDAS_PREC_FP32 && desc->method != FDAS_CONV_DIRECT)
+  if (desc->precision != FDAS_PREC_FP32 && desc->method != FDAS_CONV_DIRECT_MFMA)
     return fail(FDAS_ERR_INVALID_ARG, "split precisions apply to the direct method only");
   if (desc->hsum_index != FDAS_HSUM_STRETCH && desc->hsum_index != FDAS_HSUM_FUNDAMENTAL &&
       desc->hsum_index != FDAS_HSUM_HIGHEST)
@@ -228,7 +231,7 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
 
   std::vector<std::vector<std::complex<double>>> bank;
   fdas::template_bank(desc->z_max, bank);
-  p->direct = desc->method == FDAS_CONV_DIRECT;
+  p->direct = desc->method == FDAS_CONV_DIRECT_MFMA;
   std::vector<float> H, tw1, tw2, Bpk, tscale;
   std::vector<uint16_t> Bsp;
   std::vector<int> dtiles, drows;

@@ -15,7 +15,7 @@ struct fdas_plan {
   int L_max = 0;         // taps of the longest template
   fdas::OlsGeom geom{};  // overlap-save chunk geometry
   int conv_slots = 512;  // resident convolution workgroups (2 per compute unit)
-  bool direct = false;      // FDAS_CONV_DIRECT: matrix-core correlation instead of overlap-save
+  bool direct = false;      // FDAS_CONV_DIRECT_MFMA: matrix-core correlation instead of overlap-save
   float* d_Bpk = nullptr;   // direct: packed template operand
   int4* d_dtiles = nullptr; // direct: per-tile {P, first pair, members, 0}
   int* d_drows = nullptr;   // direct: [tiles][8] FOP rows

@@ -237,6 +237,66 @@ fdas_status fdas_prescreen_train_step(fdas_prescreen* ps, const float* d_feature
   return ok();
 }
 
+fdas_status fdas_block_closure(int64_t n, int32_t n_harm, const int32_t* h_blocks, int32_t nblocks, int32_t* h_out,
+                               int32_t capacity, int32_t* n_out) {
+  if (!n_out) return fail(FDAS_ERR_INVALID_ARG, "n_out is NULL");
+  *n_out = 0;
+  if (n < 1 || n > ((int64_t)1 << 40)) return fail(FDAS_ERR_INVALID_ARG, "n = %lld outside [1, 2^40]", (long long)n);
+  if (n_harm < 1 || n_harm > 8) return fail(FDAS_ERR_INVALID_ARG, "n_harm = %d outside [1, 8]", (int)n_harm);
+  if (nblocks < 0 || (nblocks > 0 && !h_blocks)) return fail(FDAS_ERR_INVALID_ARG, "bad block list");
+  if (capacity < 0 || (capacity > 0 && !h_out)) return fail(FDAS_ERR_INVALID_ARG, "bad output buffer");
+  const int64_t nblk = (n + kBlock - 1) / kBlock;
+  for (int i = 0; i < nblocks; ++i)
+    if (h_blocks[i] < 0 || h_blocks[i] >= nblk) return fail(FDAS_ERR_INVALID_ARG, "block %d outside the spectrum", h_blocks[i]);
+  std::vector<char> mark((size_t)nblk, 0);
+  for (int i = 0; i < nblocks; ++i) {
+    const int64_t b = h_blocks[i];
+    mark[(size_t)b] = 1;
+    // block b holds columns [4096 b, 4096 b + 4095]; harmonic m of a signal
+    // there raises the stretched sums at columns m j .. m j + m - 1
+    for (int m = 2; m <= n_harm; ++m) {
+      const int64_t lo = (int64_t)m * b * kBlock;
+      const int64_t hi = std::min<int64_t>(n - 1, (int64_t)m * ((b + 1) * kBlock - 1) + m - 1);
+      for (int64_t q = lo / kBlock; q <= hi / kBlock && q < nblk; ++q) mark[(size_t)q] = 1;
+    }
+  }
+  int32_t cnt = 0;
+  for (int64_t b = 0; b < nblk; ++b) {
+    if (!mark[(size_t)b]) continue;
+    if (cnt < capacity) h_out[cnt] = (int32_t)b;
+    ++cnt;
+  }
+  *n_out = cnt;
+  if (cnt > capacity) return fail(FDAS_ERR_CAPACITY, "closure of %d blocks > capacity %d", cnt, capacity);
+  return ok();
+}
+
+fdas_status fdas_prescreen_init_params(uint64_t seed, float* h_theta) {
+  if (!h_theta) return fail(FDAS_ERR_INVALID_ARG, "h_theta is NULL");
+  // splitmix64 (Steele, Lea & Flood 2014): state += golden gamma, then mix
+  uint64_t state = seed;
+  auto next = [&state]() {
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  // uniform in [-1, 1) from the top 53 bits
+  auto uni = [&next]() { return 2.0 * ((double)(next() >> 11) * (1.0 / 9007199254740992.0)) - 1.0; };
+  constexpr int C = 32, K = 9;
+  int o = 0;
+  for (int l = 0; l < 4; ++l) {
+    const int cin = l == 0 ? 1 : C;
+    const double lim = std::sqrt(6.0 / (cin * K));  // He-uniform bound for ReLU layers
+    for (int i = 0; i < C * cin * K; ++i) h_theta[o++] = (float)(lim * uni());
+    for (int i = 0; i < C; ++i) h_theta[o++] = 0.0f;
+  }
+  for (int i = 0; i < C; ++i) h_theta[o++] = (float)(uni() / std::sqrt((double)C));
+  h_theta[o++] = 0.0f;
+  if (o != ps_param_count()) return fail(FDAS_ERR_DEVICE, "parameter layout mismatch (%d != %d)", o, ps_param_count());
+  return ok();
+}
+
 fdas_status fdas_search_blocks(fdas_plan* p, const void* d_spectrum, int64_t n, float* d_fop, int64_t ld,
                                const int32_t* h_blocks, int32_t nblocks, fdas_cand* d_cands, int32_t* d_counts,
                                void* stream) {
@@ -344,8 +404,13 @@ fdas_status fdas_search_flagged(fdas_plan* p, const void* d_spectrum, int64_t n,
   if (st != FDAS_OK) return st;
   if (!d_cands || reinterpret_cast<uintptr_t>(d_cands) % 16 != 0 || !d_counts)
     return fail(FDAS_ERR_INVALID_ARG, "candidate buffers are NULL or misaligned");
-  if (!d_logits || reinterpret_cast<uintptr_t>(d_logits) % 4 != 0)
-    return fail(FDAS_ERR_INVALID_ARG, "logits pointer is NULL or misaligned");
+  if (!d_logits) {
+    // the screen is disabled: the plain search
+    st = fdas_convolve(p, d_spectrum, n, d_fop, ld, stream);
+    if (st == FDAS_OK) st = fdas_harmonic_sum(p, d_fop, n, ld, nullptr, d_cands, d_counts, stream);
+    return st;
+  }
+  if (reinterpret_cast<uintptr_t>(d_logits) % 4 != 0) return fail(FDAS_ERR_INVALID_ARG, "logits pointer is misaligned");
   const int64_t nblk = (n + kBlock - 1) / kBlock;
   if (nblk > kMaxSelBlocks)
     return fail(FDAS_ERR_INVALID_ARG, "n = %lld has more than %d blocks of %d bins", (long long)n, kMaxSelBlocks,

@@ -18,10 +18,13 @@ namespace {
 
 constexpr int HS_THREADS = 256;
 
+// Appends one record to list k.  A plan keeps (2 z_max + 1) n_max below 2^31,
+// so a count cannot wrap; the unsigned compare still keeps any slot that is
+// not in [0, cap) from being written.
 __device__ __forceinline__ void emit(int k, int i, int j, float p, fdas_cand* __restrict__ cands, int cap,
                                      int32_t* __restrict__ counts) {
   const int slot = atomicAdd(&counts[k - 1], 1);
-  if (slot < cap) {
+  if ((unsigned)slot < (unsigned)cap) {
     int4 rec = make_int4(k, i, j, __float_as_int(p));
     *reinterpret_cast<int4*>(cands + (size_t)(k - 1) * cap + slot) = rec;
   }
@@ -472,7 +475,7 @@ __device__ __forceinline__ void hs_emit_row(const float* __restrict__ fop, int64
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         if (j0 + a < n && hk[m][a] > t) {
-          if (slot < cap)
+          if ((unsigned)slot < (unsigned)cap)
             *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
                 make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
           ++slot;
@@ -544,7 +547,7 @@ __device__ __forceinline__ void hs_emit_wave(const float* __restrict__ fop, int6
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
       if ((hits >> (4 * (m - 1) + a)) & 1u) {
-        if (slot < cap)
+        if ((unsigned)slot < (unsigned)cap)
           *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) =
               make_int4(m, i, j0 + a, __float_as_int(hk[m][a]));
         ++slot;

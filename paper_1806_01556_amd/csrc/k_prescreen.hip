@@ -572,7 +572,8 @@ __global__ void k_ps_zero(float* __restrict__ p, int n) {
 // lists = [searched chunks, cap_c][tiles, cap_t, tail -1][source-only chunks,
 //          cap_c][n_searched_chunks, n_tiles, n_source_chunks]
 // The same selection as the host side of fdas_search_blocks with the
-// closure of the flagged blocks as its list.
+// closure of the flagged blocks as its list.  A NaN threshold or a logit that
+// is not finite selects every block (the plain search).
 constexpr int kSelThreads = 1024;
 constexpr int kPsBlock = PBLK;
 
@@ -602,14 +603,24 @@ __global__ __launch_bounds__(kSelThreads) void k_ps_search_lists(const float* __
   __shared__ unsigned char s_search[kMaxSelBlocks];
   __shared__ unsigned char s_src[kMaxSelBlocks];
   __shared__ int s_scan[kSelThreads];
+  __shared__ int s_all;
   const int t = threadIdx.x;
+  // Fallback to the plain search: a NaN threshold or any logit that is not
+  // finite (a diverged or broken model) searches every block.
+  if (t == 0) s_all = thr != thr ? 1 : 0;
+  __syncthreads();
   for (int b = t; b < nblk; b += kSelThreads) {
     s_search[b] = 0;
     s_src[b] = 0;
+    if (!(fabsf(logits[b]) <= 3.402823466e38f)) s_all = 1;  // NaN or +-inf
   }
   __syncthreads();
   for (int f = t; f < nblk; f += kSelThreads) {
-    if (!(logits[f] > thr)) continue;  // NaN never flags
+    if (s_all) {
+      s_search[f] = 1;
+      continue;
+    }
+    if (!(logits[f] > thr)) continue;
     s_search[f] = 1;
     for (int m = 2; m <= nh; ++m) {
       const int64_t lo = (int64_t)m * f * kPsBlock;

@@ -21,7 +21,7 @@ STATUS_NAMES = {
     0: "FDAS_OK", 1: "FDAS_ERR_INVALID_ARG", 2: "FDAS_ERR_NO_DEVICE", 3: "FDAS_ERR_OUT_OF_MEMORY",
     4: "FDAS_ERR_DEVICE", 5: "FDAS_ERR_CAPACITY", 6: "FDAS_ERR_UNSUPPORTED",
 }
-CONV_AUTO, CONV_OLS_FFT, CONV_DIRECT = 0, 1, 2
+CONV_AUTO, CONV_OLS_FFT, CONV_DIRECT_MFMA = 0, 1, 2
 PREC_FP32, PREC_SPLIT_FP16, PREC_SPLIT_BF16 = 0, 1, 2
 HSUM_STRETCH, HSUM_FUNDAMENTAL, HSUM_HIGHEST = 0, 1, 2
 
@@ -33,18 +33,19 @@ EXPORTED = (
     "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped", "fdas_prescreen_param_count",
     "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params", "fdas_prescreen_get_params",
     "fdas_prescreen_features", "fdas_prescreen_forward", "fdas_prescreen_infer", "fdas_prescreen_gradient",
-    "fdas_prescreen_train_step", "fdas_search_blocks", "fdas_search_flagged",
+    "fdas_prescreen_train_step", "fdas_search_blocks", "fdas_search_flagged", "fdas_block_closure",
+    "fdas_prescreen_init_params",
 )
 
 
 class PlanDesc(ctypes.Structure):
     _fields_ = [
         ("struct_size", ctypes.c_int32),
-        ("z_max", ctypes.c_int32),
         ("n_max", ctypes.c_int64),
+        ("z_max", ctypes.c_int32),
         ("n_harm", ctypes.c_int32),
-        ("cand_capacity", ctypes.c_int32),
         ("p_fa", ctypes.c_double),
+        ("cand_capacity", ctypes.c_int32),
         ("top_k", ctypes.c_int32),
         ("method", ctypes.c_int32),
         ("precision", ctypes.c_int32),
@@ -134,13 +135,15 @@ def lib():
     L.fdas_prescreen_train_step.argtypes = [vp, vp, vp, i32, flt, flt, vp, vp, vp]
     L.fdas_search_blocks.argtypes = [vp, vp, i64, vp, i64, vp, i32, vp, vp, vp]
     L.fdas_search_flagged.argtypes = [vp, vp, i64, vp, i64, vp, ctypes.c_float, vp, vp, vp]
+    L.fdas_block_closure.argtypes = [i64, i32, vp, i32, vp, i32, ctypes.POINTER(i32)]
+    L.fdas_prescreen_init_params.argtypes = [ctypes.c_uint64, vp]
     for name in ("fdas_plan_create", "fdas_plan_destroy", "fdas_convolve", "fdas_harmonic_sum",
                  "fdas_candidates", "fdas_template_taps", "fdas_thresholds", "fdas_search_batch",
                  "fdas_candidates_batch", "fdas_autotune", "fdas_set_tuning", "fdas_candidates_mapped",
                  "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params",
                  "fdas_prescreen_get_params", "fdas_prescreen_features", "fdas_prescreen_forward",
                  "fdas_prescreen_infer", "fdas_prescreen_gradient", "fdas_prescreen_train_step", "fdas_search_blocks",
-                 "fdas_search_flagged"):
+                 "fdas_search_flagged", "fdas_block_closure", "fdas_prescreen_init_params"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -418,15 +421,11 @@ class Prescreen:
                                                float(lr), _ptr(logits), _ptr(loss), _stream(stream)))
 
 
-def init_prescreen_params(seed=0):
-    """He-uniform convolution weights, small head weights, zero biases (float32)."""
-    rng = np.random.default_rng(seed)
-    parts = []
-    for cin in (1, 32, 32, 32):
-        lim = np.sqrt(6.0 / (cin * 9))
-        parts += [rng.uniform(-lim, lim, size=32 * cin * 9), np.zeros(32)]
-    parts += [rng.uniform(-1.0, 1.0, size=32) / np.sqrt(32.0), np.zeros(1)]
-    return np.concatenate(parts).astype(np.float32)
+def prescreen_init_params(seed=0):
+    """Initial network parameters from the library (float32[param_count])."""
+    out = np.zeros(int(lib().fdas_prescreen_param_count()), dtype=np.float32)
+    _check(lib().fdas_prescreen_init_params(int(seed), out.ctypes.data))
+    return out
 
 
 def search_blocks(plan, spectrum, n, fop, blocks, cands, counts, ld=None, stream=None):
@@ -440,27 +439,23 @@ def search_blocks(plan, spectrum, n, fop, blocks, cands, counts, ld=None, stream
 
 def search_flagged(plan, spectrum, n, fop, logits, threshold, cands, counts, ld=None, stream=None):
     """The restricted search on the blocks whose logit exceeds threshold, plus
-    their harmonic closure, selected on the device (asynchronous)."""
+    their harmonic closure, selected on the device (asynchronous).  logits None
+    (screen disabled), a non-finite logit or a NaN threshold search every block."""
     if ld is None:
         ld = fop.shape[1]
     _check(lib().fdas_search_flagged(plan.handle, _ptr(spectrum), int(n), _ptr(fop), int(ld), _ptr(logits),
                                      float(threshold), _ptr(cands), _ptr(counts), _stream(stream)))
 
 
-def harmonic_closure(blocks, n, n_harm=8):
-    """Blocks plus the blocks holding their harmonic multiples m*j, m = 2..n_harm.
-
-    Under the stretch index map a strong signal at column j raises harmonic
-    sums at columns m*j .. m*j + m - 1, so a block flagged for a signal also
-    needs the blocks of its multiples searched."""
-    nblk = (int(n) + BLOCK - 1) // BLOCK
-    out = set(int(b) for b in blocks)
-    for b in list(out):
-        for m in range(2, n_harm + 1):
-            lo, hi = m * b * BLOCK, min(int(n) - 1, m * ((b + 1) * BLOCK - 1) + m - 1)
-            for q in range(lo // BLOCK, min(nblk - 1, hi // BLOCK) + 1):
-                out.add(q)
-    return np.array(sorted(out), dtype=np.int32)
+def block_closure(blocks, n, n_harm=8):
+    """The library's harmonic closure of a block list (sorted int32 array)."""
+    blocks = np.ascontiguousarray(blocks, dtype=np.int32)
+    cap = (int(n) + BLOCK - 1) // BLOCK
+    out = np.zeros(max(cap, 1), dtype=np.int32)
+    cnt = ctypes.c_int32(0)
+    _check(lib().fdas_block_closure(int(n), int(n_harm), blocks.ctypes.data if blocks.size else None, blocks.size,
+                                    out.ctypes.data, cap, ctypes.byref(cnt)))
+    return out[:cnt.value].copy()
 
 
 # ---- torch conveniences ------------------------------------------------------

@@ -165,7 +165,7 @@ def test_top_k_per_trial():
 
 @pytest.mark.parametrize("kind", ["direct", "z_max_5", "fundamental"])
 def test_batch_on_plans_without_the_graphed_path(kind):
-    kw = {"direct": {"method": fdas.CONV_DIRECT}, "z_max_5": {"z_max": 5},
+    kw = {"direct": {"method": fdas.CONV_DIRECT_MFMA}, "z_max_5": {"z_max": 5},
           "fundamental": {"hsum_index": fdas.HSUM_FUNDAMENTAL}}[kind]
     plan = fdas.plan_create(n_max=1 << 17, **kw)
     try:

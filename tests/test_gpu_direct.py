@@ -1,6 +1,6 @@
 """GPU parity of the direct (matrix-core) correlation against the CPU oracle.
 
-fdas_convolve with method FDAS_CONV_DIRECT computes the same plane as the
+fdas_convolve with method FDAS_CONV_DIRECT_MFMA computes the same plane as the
 overlap-save method (eq. (1) of Section 2.1 evaluated as a sum over taps), so
 it is held to the same bound: |P - P_ref| <= 1e-4 * max(P_ref, 1) for every
 cell, against the FP64 oracle.  The kernel works on 512-bin workgroups and
@@ -17,6 +17,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+import skaref  # noqa: E402
 from oracle import fop as ofop  # noqa: E402
 from oracle import harmonic as oh  # noqa: E402
 from paper_1806_01556_amd import fdas, synth  # noqa: E402
@@ -33,7 +34,7 @@ def _dev():
 def direct_plan(z_max=42, n_max=1 << 22):
     key = (z_max, n_max)
     if key not in _plans:
-        _plans[key] = fdas.plan_create(z_max=z_max, n_max=n_max, method=fdas.CONV_DIRECT)
+        _plans[key] = fdas.plan_create(z_max=z_max, n_max=n_max, method=fdas.CONV_DIRECT_MFMA)
     return _plans[key]
 
 
@@ -95,19 +96,18 @@ def test_direct_plain_workload_full_plane_and_candidates():
     assert (1, 17, 20000) in gk or (1, 18, 20000) in gk
 
 
-def test_direct_ska_size_sampled():
-    # full SKA length in one launch; sampled cells against the direct sum,
-    # including workgroup boundaries and the tail
+@pytest.mark.timeout(900)
+def test_direct_ska_size_full_plane():
+    # full SKA length in one launch: every one of the 85 x 2^22 cells against
+    # the FP64 oracle, plus workgroup-boundary columns against the direct sum
     plan = direct_plan()
-    spec, _ = synth.ska()
+    spec, _, plane64, _, _, _ = skaref.ska()
     n = spec.shape[0]
     got = gpu_fop(plan, spec).cpu().numpy()
-    rng = np.random.default_rng(9)
-    cols = np.concatenate([rng.integers(0, n, 1000), [0, 1, 511, 512, 513, 8191, 8192, n - 513, n - 512, n - 1]])
-    rows = rng.integers(0, 85, cols.size)
-    assert_fop_close(got[rows, cols], ofop.fop_points(spec.astype(np.complex128), rows, cols))
-    cc = np.repeat(np.array([4095 * 512 - 1, 4095 * 512]), 85)
-    rr = np.tile(np.arange(85), 2)
+    worst = skaref.assert_plane_close(got, plane64)
+    print(f"direct, ska 2^22, all {85 * n} cells: worst |err|/bound = {worst:.3g}", flush=True)
+    cc = np.repeat(np.array([0, 511, 512, 4095 * 512 - 1, 4095 * 512, n - 1]), 85)
+    rr = np.tile(np.arange(85), 6)
     assert_fop_close(got[rr, cc], ofop.fop_points(spec.astype(np.complex128), rr, cc))
 
 

@@ -45,9 +45,9 @@ def plan_for(prec, z_max=42, n_max=1 << 22):
         if prec == "ols":
             _plans[key] = fdas.plan_create(z_max=z_max, n_max=n_max, method=fdas.CONV_OLS_FFT)
         elif prec == "fp32":
-            _plans[key] = fdas.plan_create(z_max=z_max, n_max=n_max, method=fdas.CONV_DIRECT)
+            _plans[key] = fdas.plan_create(z_max=z_max, n_max=n_max, method=fdas.CONV_DIRECT_MFMA)
         else:
-            _plans[key] = fdas.plan_create(z_max=z_max, n_max=n_max, method=fdas.CONV_DIRECT, precision=PREC[prec])
+            _plans[key] = fdas.plan_create(z_max=z_max, n_max=n_max, method=fdas.CONV_DIRECT_MFMA, precision=PREC[prec])
     return _plans[key]
 
 

@@ -6,6 +6,10 @@
   evaluated with the BF16-rounded parameters the kernels use: the kernels
   accumulate in FP32, so logits agree to ~1e-5 relative and each gradient
   tensor to ~1e-4 of its norm (the bounds below leave a factor of ~10).
+* Adam: every step of k_ps_adam against a NumPy bias-corrected Adam driven by
+  the oracle gradient at the parameters the kernels use; the BF16 copy the
+  kernels compute with is refreshed (logits after the update match the
+  oracle network at the updated parameters).
 * A few Adam steps on a separable toy set lower the loss.
 * fdas_prescreen_infer (features computed in the inference kernel) gives the
   logits of fdas_prescreen_features + fdas_prescreen_forward bit for bit, for
@@ -15,9 +19,11 @@
   (bit-identical powers), since each searched column's harmonic sum reads
   convolved columns only.
 * fdas_search_flagged (block selection on the device) returns exactly what
-  fdas_search_blocks returns for the harmonic closure of the flagged blocks,
-  for random logits and ragged lengths; no flagged block gives no
-  candidates, every block the plain search; NaN logits never flag.
+  fdas_search_blocks returns for the harmonic closure of the flagged blocks
+  (the closure computed by brute force in the test), for random logits and
+  ragged lengths; no flagged block gives no candidates, every block the plain
+  search.  Fallback: a disabled screen (no logits), NaN or infinite logits
+  and a NaN threshold all give exactly the plain search.
 """
 
 import numpy as np
@@ -27,6 +33,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+from blockref import closure_reference  # noqa: E402
 from oracle import prescreen as ops  # noqa: E402
 from paper_1806_01556_amd import fdas, synth  # noqa: E402
 
@@ -53,7 +60,7 @@ def _blocks(nb, seed):
 
 
 def _theta(seed):
-    th = fdas.init_prescreen_params(seed)
+    th = fdas.prescreen_init_params(seed)
     th[-33:-1] *= 4.0  # a livelier head for the checks
     return th
 
@@ -86,7 +93,15 @@ def test_features_match_numpy():
 
 
 def test_forward_and_gradient_match_oracle():
-    nb = 6
+    """Logits, loss and gradient over 40 blocks.  The gradient routes through
+    max-pool positions and ReLU signs, decisions taken in FP32 on the GPU and
+    in FP64 by the oracle: a near tie decided the other way moves a block's
+    contribution to the weights of its channel.  The oracle itself moves its
+    layer-1 weight gradient by 2.8e-3 of the norm under a 1e-5 relative
+    perturbation of the weights (1.4e-6 under 1e-6: no decision changes), so
+    the batch mean is held to 5e-3 per tensor, and block by block (one block
+    per call) at least 90 % of the blocks agree to 1e-3 per tensor."""
+    nb = 40
     X, y = _blocks(nb, 5)
     theta = _theta(1)
     th_b = bf16_round(theta)  # what the kernels compute with
@@ -107,10 +122,25 @@ def test_forward_and_gradient_match_oracle():
         assert abs(float(loss.item()) - ref_loss) <= 1e-4 * (1.0 + ref_loss)
         g = grad.cpu().numpy().astype(np.float64)
         offs = np.cumsum([0] + [int(np.prod(s)) for s in ops.param_shapes()])
-        for i in range(len(offs) - 1):
-            a, b = g[offs[i]:offs[i + 1]], ref_grad[offs[i]:offs[i + 1]]
-            scale = max(np.linalg.norm(b), 1e-12)
-            assert np.linalg.norm(a - b) <= 1e-3 * scale + 1e-9, (i, np.linalg.norm(a - b), scale)
+
+        def rel_errs(a, b):
+            return [np.linalg.norm(a[offs[i]:offs[i + 1]] - b[offs[i]:offs[i + 1]]) /
+                    max(np.linalg.norm(b[offs[i]:offs[i + 1]]), 1e-12) for i in range(len(offs) - 1)]
+
+        e = rel_errs(g, ref_grad)
+        print("batch gradient, relative error per tensor:", [f"{v:.1e}" for v in e], flush=True)
+        assert max(e) <= 5e-3, e
+        # block by block
+        good, worst = 0, 0.0
+        g1 = torch.zeros(ps.param_count(), device=_dev())
+        for b in range(nb):
+            ps.gradient(xf[b:b + 1], yl[b:b + 1], 1, 3.0, logits[b:b + 1], loss, g1)
+            _, rg = ops.batch_loss_grad(th_b, X[b:b + 1].astype(np.float64), y[b:b + 1], 3.0)
+            eb = max(rel_errs(g1.cpu().numpy().astype(np.float64), rg))
+            good += eb <= 1e-3
+            worst = max(worst, eb)
+        print(f"per block: {good} of {nb} within 1e-3 per tensor, worst {worst:.2e}", flush=True)
+        assert good >= 0.9 * nb and worst <= 5e-2
         # the inference call (32-channel layers on the matrix cores, activations
         # as BF16 hi + lo pairs: ~2^-17 relative per activation) agrees too
         l2 = torch.zeros(nb, device=_dev())
@@ -127,7 +157,7 @@ def test_training_lowers_the_loss():
     X, y = _blocks(nb, 9)
     ps = fdas.Prescreen(max_batch=nb)
     try:
-        ps.set_params(fdas.init_prescreen_params(2))
+        ps.set_params(fdas.prescreen_init_params(2))
         xf = torch.from_numpy(X).to(_dev())
         yl = torch.from_numpy(y).to(_dev())
         logits = torch.zeros(nb, device=_dev())
@@ -222,24 +252,104 @@ def test_search_flagged_equals_search_blocks_of_the_closure(n, seed):
     thr = 1.3
     flagged = np.nonzero(logits.cpu().numpy() > thr)[0]
     got, _ = _flagged_search(plan, x, n, logits, thr)
-    ref = _blocks_search(plan, x, n, fdas.harmonic_closure(flagged, n))
+    ref = _blocks_search(plan, x, n, closure_reference(flagged, n, 8))
     _same(got, ref)
 
 
-def test_search_flagged_none_all_and_nan():
+def test_search_flagged_none_all_and_fallback():
     plan = plan42()
     n = 4096 * 50 + 7
     spec, _ = synth.make_spectrum(n, 961, n_random=3, r_range=(500, n * 0.4), snr_range=(8, 20))
     x = torch.from_numpy(spec).to(_dev())
     nblk = (n + 4095) // 4096
+    plain = _plain(plan, x, n)
     logits = torch.zeros(nblk, device=_dev())
     c, hc = _flagged_search(plan, x, n, logits, 1.0)  # nothing flagged
     assert c.size == 0 and not np.any(hc)
     c, _ = _flagged_search(plan, x, n, logits, -1.0)  # every block
-    _same(c, _plain(plan, x, n))
-    nan = torch.full((nblk,), float("nan"), device=_dev())
-    c, hc = _flagged_search(plan, x, n, nan, -1e30)
-    assert c.size == 0 and not np.any(hc)
+    _same(c, plain)
+    # a broken model falls back to the plain search: NaN or infinite logits
+    # (one bad block is enough), a NaN threshold, or no logits at all
+    for bad in (float("nan"), float("inf"), float("-inf")):
+        lg = torch.full((nblk,), -5.0, device=_dev())
+        lg[nblk // 2] = bad
+        c, _ = _flagged_search(plan, x, n, lg, 1.0)
+        _same(c, plain)
+    c, _ = _flagged_search(plan, x, n, torch.full((nblk,), float("nan"), device=_dev()), -1e30)
+    _same(c, plain)
+    c, _ = _flagged_search(plan, x, n, logits, float("nan"))
+    _same(c, plain)
+    c, _ = _flagged_search(plan, x, n, None, 1.0)
+    _same(c, plain)
+
+
+def test_adam_steps_match_numpy_adam():
+    """Each train_step applies Adam (beta 0.9 / 0.999, eps 1e-8, bias
+    correction) to the FP32 master parameters with the mean gradient of the
+    batch at the BF16 copy.  Two references, step by step from the parameters
+    the GPU holds:
+    * NumPy Adam driven by the gradient the GPU computes at those parameters
+      (fdas_prescreen_gradient): the update itself, so every component whose
+      gradient is not lost in the summation noise of the float atomics agrees
+      to 1e-3 of lr;
+    * NumPy Adam driven by the oracle gradient at the BF16 rounding of those
+      parameters: 95 % of the components agree to 5e-2 of lr (the rest are
+      components the FP32 / FP64 max-pool and ReLU decisions move, see the
+      gradient test), and no update differs by more than 2 lr (an Adam step
+      is at most about lr per component)."""
+    nb, lr, steps = 8, 1e-3, 5
+    b1, b2, eps = 0.9, 0.999, 1e-8
+    X, y = _blocks(nb, 21)
+    ps = fdas.Prescreen(max_batch=nb)
+    try:
+        theta = _theta(5)
+        ps.set_params(theta)
+        xf = torch.from_numpy(X).to(_dev())
+        yl = torch.from_numpy(y).to(_dev())
+        logits = torch.zeros(nb, device=_dev())
+        loss = torch.zeros(1, device=_dev())
+        gbuf = torch.zeros(ps.param_count(), device=_dev())
+        m_g, v_g = np.zeros(theta.size), np.zeros(theta.size)
+        m_o, v_o = np.zeros(theta.size), np.zeros(theta.size)
+        offs = np.cumsum([0] + [int(np.prod(s)) for s in ops.param_shapes()])
+        cur = ps.get_params().astype(np.float64)
+        assert np.array_equal(cur, theta.astype(np.float64))
+        for t in range(1, steps + 1):
+            ps.gradient(xf, yl, nb, 2.0, logits, loss, gbuf)
+            g_gpu = gbuf.cpu().numpy().astype(np.float64)
+            _, g_or = ops.batch_loss_grad(bf16_round(cur), X.astype(np.float64), y, 2.0)
+            c1, c2 = 1 - b1 ** t, 1 - b2 ** t
+            m_g = b1 * m_g + (1 - b1) * g_gpu
+            v_g = b2 * v_g + (1 - b2) * g_gpu * g_gpu
+            m_o = b1 * m_o + (1 - b1) * g_or
+            v_o = b2 * v_o + (1 - b2) * g_or * g_or
+            step_g = lr * (m_g / c1) / (np.sqrt(v_g / c2) + eps)
+            step_o = lr * (m_o / c1) / (np.sqrt(v_o / c2) + eps)
+            ps.train_step(xf, yl, nb, 2.0, lr, logits, loss)
+            got = ps.get_params().astype(np.float64)
+            upd = cur - got
+            dg, do = np.abs(upd - step_g), np.abs(upd - step_o)
+            assert np.all(do <= 2 * lr) and np.all(dg <= 2 * lr), (t, float(do.max()), float(dg.max()))
+            assert np.mean(do <= 5e-2 * lr) >= 0.95, (t, float(np.mean(do <= 5e-2 * lr)))
+            for i in range(len(offs) - 1):
+                sl = slice(offs[i], offs[i + 1])
+                clear = np.abs(g_gpu[sl]) >= 1e-3 * np.linalg.norm(g_gpu[sl])
+                if clear.any():
+                    # FP32 master parameters: one rounding of theta on top
+                    tol = 1e-3 * lr + 2.0 ** -23 * np.abs(got[sl][clear])
+                    assert np.all(dg[sl][clear] <= tol), (t, i, float(np.max(dg[sl][clear])))
+            print(f"adam step {t}: max |update - ref| {dg.max():.2g} (gpu gradient), "
+                  f"{do.max():.2g} (oracle gradient), lr {lr}", flush=True)
+            cur = got
+        # the kernels now compute with the BF16 rounding of the updated parameters
+        l2 = torch.zeros(nb, device=_dev())
+        ps.forward(xf, nb, l2)
+        torch.cuda.synchronize()
+        ref_logits = np.array([ops.forward(bf16_round(cur), X[i].astype(np.float64))[0] for i in range(nb)])
+        got2 = l2.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got2 - ref_logits) <= 1e-4 * (1.0 + np.abs(ref_logits)))
+    finally:
+        ps.destroy()
 
 
 def test_inference_over_many_samples_matches_training_forward():

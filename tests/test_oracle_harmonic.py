@@ -168,3 +168,97 @@ def test_column_window_equals_restriction_of_full_plane():
     win = harmonic.candidates(p, 8, cols=w)
     sel = full[(full["r"] >= 2000) & (full["r"] < 3500)]
     assert win.size > 1000 and np.array_equal(sel, win)
+
+
+def _guard_pin_plane(ta, n=4000):
+    """A 2*4+1-row plane of zeros whose harmonic sums sit at chosen distances
+    from the thresholds.  Every set cell has column j >= n/2, so the stretched
+    sources floor(j/k) < n/2 of every plane k >= 2 are zero and HP_k(i, j) is
+    the cell's own value for every k, except the last group, which also sets
+    the source floor(j/2) so that only HP_2 (and higher) carries the sum."""
+    z_max, rows = 4, 9
+    p = np.zeros((rows, n))
+    placed = []  # (k, z, r, value, expected in the band of plane k)
+    j = n // 2
+    for k in range(1, ta.shape[0] + 1):
+        for z in (-4, -1, 0, 3):
+            t = ta[k - 1, z + z_max]
+            for f, inside in ((1 + 0.5e-4, True), (1 - 0.5e-4, True), (1 + 2e-4, False), (1 - 2e-4, False)):
+                p[z + z_max, j] = t * f
+                placed.append((k, z, j, t * f, inside))
+                j += 3
+    # HP_2 = a + b with a at (z, j) and b at its k = 2 source (trunc(z/2), floor(j/2))
+    extra = []
+    for z in (2, -3):
+        jj = j + (j % 2)
+        a = 1.0
+        b = ta[1, z + z_max] * (1 + 0.3e-4) - a
+        p[z + z_max, jj] = a
+        p[int(np.trunc(z / 2)) + z_max, jj // 2] = b
+        extra.append((z, jj))
+        j = jj + 4
+    assert j < n
+    return p, placed, extra
+
+
+@pytest.mark.parametrize("row_dependent", [False, True])
+def test_guard_cells_band_width_and_plane(row_dependent):
+    """guard_cells keeps exactly the cells whose FP64 HP_k is within 1e-4 T of
+    plane k's own threshold TA(k, i): 0.5e-4 T away is in, 2e-4 T is out, for
+    every k, for negative, zero and positive rows, and for a threshold that
+    depends on the row; a sum of two cells is judged on HP_2, not on the FOP."""
+    ta = harmonic.threshold_array(8, 4, 1e-6)
+    if row_dependent:
+        ta = ta * (1.0 + 0.03 * np.arange(9)[None, :])
+    p, placed, extra = _guard_pin_plane(ta)
+    guard = harmonic.guard_cells(p, 8, ta=ta)
+    for k, z, r, v, inside in placed:
+        assert ((k, z, r) in guard) == inside, (k, z, r, v / ta[k - 1, z + 4])
+        # the value is never within the band of another plane's threshold
+        for k2 in range(1, 9):
+            if k2 != k:
+                assert (k2, z, r) not in guard
+    for z, jj in extra:
+        assert (2, z, jj) in guard and (1, z, jj) not in guard
+    # one pass gives the same list and band
+    c1 = harmonic.candidates(p, 8, ta=ta)
+    c2, g2 = harmonic.candidates_and_guard(p, 8, ta=ta)
+    assert g2 == guard
+    assert np.array_equal(c1, c2)
+    # the cells just above threshold are candidates of their plane
+    keys = set(zip(c1["harm"].tolist(), c1["z"].tolist(), c1["r"].tolist()))
+    for k, z, r, v, inside in placed:
+        if v > ta[k - 1, z + 4]:
+            assert (k, z, r) in keys
+
+
+def test_candidates_and_guard_one_pass_matches_on_noise():
+    rng = np.random.default_rng(44)
+    plane = rng.exponential(size=(85, 30000))
+    ta = harmonic.threshold_array(8, 42, 1e-3)
+    c, g = harmonic.candidates_and_guard(plane, 8, ta=ta, rel=1e-2)
+    assert np.array_equal(c, harmonic.candidates(plane, 8, ta=ta))
+    assert g == harmonic.guard_cells(plane, 8, ta=ta, rel=1e-2)
+    assert len(g) > 50
+    cols = np.arange(1000, 9000)
+    c, g = harmonic.candidates_and_guard(plane, 8, ta=ta, rel=1e-2, cols=cols)
+    assert np.array_equal(c, harmonic.candidates(plane, 8, ta=ta, cols=cols))
+    assert g == harmonic.guard_cells(plane, 8, ta=ta, rel=1e-2, cols=cols)
+
+
+def test_guard_count_on_noise_matches_the_band_density():
+    """On exponential noise the band holds about rows * n * f_k(T_k) * 2 rel T_k
+    cells per plane (a wide band, rel = 0.02, so the count is large), and
+    about rel / wide of the cells of a band `wide` times as wide."""
+    rng = np.random.default_rng(45)
+    n = 200000
+    plane = rng.exponential(size=(85, n))
+    _, g, w = harmonic.candidates_and_guard(plane, 1, p_fa=1e-3, rel=0.02, wide=0.2)
+    from skaref import expected_guard_count
+    mean = expected_guard_count(n, n_harm=1, p_fa=1e-3, rel=0.02)
+    assert abs(len(g) - mean) <= 5 * np.sqrt(mean), (len(g), mean)
+    # the density is not flat over +-20 %: Gamma(1) falls by e^{+-0.2 T}; the
+    # band population of the exponential is exact, 2 sinh(0.2 T) e^{-T} per cell
+    T = harmonic.thresholds(1, 1e-3)[0]
+    wide_mean = 85 * n * 2 * np.sinh(0.2 * T) * np.exp(-T)
+    assert abs(w[0] - wide_mean) <= 5 * np.sqrt(wide_mean), (w[0], wide_mean)
