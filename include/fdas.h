@@ -154,6 +154,20 @@ fdas_status fdas_harmonic_sum(fdas_plan* plan, const float* d_fop, int64_t n, in
                               const float* d_ta, fdas_cand* d_cands, int32_t* d_counts,
                               void* stream);
 
+/* fdas_harmonic_sum for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops and harnesses that forbid
+ * hipMalloc.  Same arguments, kernels and results as fdas_harmonic_sum; it
+ * calls no allocating routine.  Its scratch (hit-row counter, tile order and
+ * hit-row list, 16.02 MiB) is a static device array of the library, one per
+ * GPU, held until the process ends; calls that overlap on one GPU share it
+ * and race, so they must be ordered (one stream, or events).  The array keeps
+ * the last call's contents; every call clears the counter and rewrites the
+ * tile order with kernels (no memset).  n <= 2^22 (FDAS_ERR_INVALID_ARG
+ * otherwise).  Asynchronous on stream. */
+fdas_status fdas_harmonic_sum_noalloc(fdas_plan* plan, const float* d_fop, int64_t n, int64_t ld,
+                                      const float* d_ta, fdas_cand* d_cands, int32_t* d_counts,
+                                      void* stream);
+
 /* Copy the candidate lists back (after the work queued on stream), order them
  * by (harm, z, r) and write at most h_capacity records to h_out.  With
  * top_k > 0 each plane keeps its top_k highest powers (ties: lower z, then

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -100,6 +101,31 @@ void keep_top_k(const fdas_cand* sorted, const int* off, int nh, int top_k, std:
     }
     keep.insert(keep.end(), v.begin(), v.end());
   }
+}
+
+// Device address of the static scratch array of fdas_harmonic_sum_noalloc,
+// resolved once per device (at the first plan created on it, with the device
+// current) and kept for the life of the process.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t resolve_noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  hipError_t e = harmsum_noalloc_scratch(&ptr);
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 hipError_t tile_order_for(fdas_plan* p, int64_t n, const int** d_order, int* blocks) {
@@ -227,6 +253,10 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
       p->conv_slots = 2 * cus;
+  }
+  if ((e = fdas::resolve_noalloc_scratch(p->device)) != hipSuccess) {
+    free_plan(p);
+    return hip_fail(e, "resolving the static scratch address");
   }
 
   std::vector<std::vector<std::complex<double>>> bank;
@@ -359,6 +389,30 @@ fdas_status fdas_harmonic_sum(fdas_plan* p, const float* d_fop, int64_t n, int64
   e = fdas::launch_harmsum(d_fop, n, ld, p->desc.z_max, p->desc.n_harm, d_ta ? d_ta : p->d_ta, d_cands,
                            p->desc.cand_capacity, d_counts, wk, p->desc.hsum_index, s);
   if (e != hipSuccess) return hip_fail(e, "launching the harmonic sum");
+  return ok();
+}
+
+fdas_status fdas_harmonic_sum_noalloc(fdas_plan* p, const float* d_fop, int64_t n, int64_t ld, const float* d_ta,
+                                      fdas_cand* d_cands, int32_t* d_counts, void* stream) {
+  if (!p) return fail(FDAS_ERR_INVALID_ARG, "plan is NULL");
+  fdas_status st = check_fop_args(p, d_fop, n, ld);
+  if (st != FDAS_OK) return st;
+  if (n > fdas::harmsum_noalloc_max_n())
+    return fail(FDAS_ERR_INVALID_ARG, "n = %lld exceeds the %lld bins the static scratch of the allocation-free "
+                "harmonic sum holds", (long long)n, (long long)fdas::harmsum_noalloc_max_n());
+  if (!d_cands) return fail(FDAS_ERR_INVALID_ARG, "candidate buffer is NULL");
+  if (reinterpret_cast<uintptr_t>(d_cands) % 16 != 0)
+    return fail(FDAS_ERR_INVALID_ARG, "candidate buffer must be 16-byte aligned");
+  if (!d_counts) return fail(FDAS_ERR_INVALID_ARG, "count buffer is NULL");
+  void* scr = fdas::noalloc_scratch(p->device);
+  if (!scr) return fail(FDAS_ERR_DEVICE, "static scratch address of device %d was not resolved", p->device);
+  DeviceGuard dg(p->device);
+  if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
+  hipError_t e = fdas::launch_harmsum_noalloc(d_fop, n, ld, p->desc.z_max, p->desc.n_harm, d_ta ? d_ta : p->d_ta,
+                                              d_cands, p->desc.cand_capacity, d_counts, scr,
+                                              p->tuning.emit_workgroups, p->desc.hsum_index,
+                                              static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "launching the allocation-free harmonic sum");
   return ok();
 }
 

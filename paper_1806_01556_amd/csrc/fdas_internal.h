@@ -146,6 +146,16 @@ hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, in
 
 hipError_t launch_fill_i32(int32_t* p, int count, int32_t value, hipStream_t s);
 
+// Allocation-free harmonic sum: the same kernels with their scratch (hit-row
+// counter, tile order, hit-row list) in the library's static device array.
+// harmsum_noalloc_scratch returns that array's address on the current device.
+int64_t harmsum_noalloc_max_n();
+size_t harmsum_noalloc_scratch_bytes();
+hipError_t harmsum_noalloc_scratch(void** ptr);
+hipError_t launch_harmsum_noalloc(const float* fop, int64_t n, int64_t ld, int z_max, int n_harm, const float* ta,
+                                  fdas_cand* cands, int cap, int32_t* counts, void* scratch, int emit_blocks,
+                                  int index, hipStream_t s);
+
 int sort_tile_count(int m);
 int sort_passes(int rows, int bits_r);
 

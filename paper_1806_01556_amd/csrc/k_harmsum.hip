@@ -643,7 +643,69 @@ __global__ void k_fill_i32(int32_t* p, int count, int32_t value) {
   if (i < count) p[i] = value;
 }
 
+// Tile order of the 85-row kernel computed on the device (the order
+// harmsum_tile_order builds on the host): tile t has the key
+// (frac << 6) | (octave + 1), frac = (t - 2^octave) << (top - octave), key 0
+// for t = 0; tiles are ranked by key and rank q goes to workgroup
+// (q mod per) * 8 + q / per, per = ceil(T / 8).  Keys are distinct, so the
+// rank of t is the number of smaller keys.
+__device__ __forceinline__ uint64_t tile_key(int t, int top) {
+  if (t == 0) return 0;
+  const int o = 31 - __clz(t);
+  const uint64_t frac = (uint64_t)(t - (1 << o)) << (top - o);
+  return (frac << 6) | (uint64_t)(o + 1);
+}
+
+__global__ void k_tile_order(int* __restrict__ order, int T, int top, int per) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const uint64_t k = tile_key(t, top);
+  int q = 0;
+  for (int u = 0; u < T; ++u) q += tile_key(u, top) < k ? 1 : 0;
+  order[(q % per) * 8 + q / per] = t;
+}
+
+// Scratch of fdas_harmonic_sum_noalloc in static device memory (one copy per
+// GPU, kept until the process ends): hit-row counter, tile order, hit-row list.
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 22;
+constexpr size_t kNaOrderOff = 256;
+constexpr size_t kNaOrderInts = ((size_t)kNoAllocMaxN / (4 * HS_THREADS) + 8 + 63) / 64 * 64;
+constexpr size_t kNaHitOff = kNaOrderOff + kNaOrderInts * sizeof(int);
+constexpr size_t kNaBytes = kNaHitOff + (size_t)(kNoAllocMaxN / 4) * sizeof(int4);
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
 }  // namespace
+
+int64_t harmsum_noalloc_max_n() { return kNoAllocMaxN; }
+size_t harmsum_noalloc_scratch_bytes() { return kNaBytes; }
+
+hipError_t harmsum_noalloc_scratch(void** ptr) {
+  // the caller has made the device current; the address is per device
+  return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
+hipError_t launch_harmsum_noalloc(const float* fop, int64_t n, int64_t ld, int z_max, int n_harm, const float* ta,
+                                  fdas_cand* cands, int cap, int32_t* counts, void* scr, int emit_blocks,
+                                  int index, hipStream_t s) {
+  if (n < 1 || n > kNoAllocMaxN || !scr) return hipErrorInvalidValue;
+  unsigned char* base = static_cast<unsigned char*>(scr);
+  int* order = reinterpret_cast<int*>(base + kNaOrderOff);
+  int4* hitrows = reinterpret_cast<int4*>(base + kNaHitOff);
+  int32_t* hit_count = reinterpret_cast<int32_t*>(base);
+  const int cols = 4 * HS_THREADS;
+  const int T = (int)((n + cols - 1) / cols);
+  const int per = (T + 7) / 8;
+  if (z_max == 42 && index == FDAS_HSUM_STRETCH) {
+    int top = 0;
+    while ((1LL << (top + 1)) <= (int64_t)(T > 2 ? T - 1 : 1)) ++top;
+    hipError_t e = launch_fill_i32(order, per * 8, -1, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_tile_order, dim3((T + 255) / 256), dim3(256), 0, s, order, T, top, per);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const HsWork wk{order, per * 8, hitrows, hit_count, emit_blocks};
+  return launch_harmsum(fop, n, ld, z_max, n_harm, ta, cands, cap, counts, wk, index, s);
+}
 
 int harmsum_tile_columns() { return 4 * HS_THREADS; }
 

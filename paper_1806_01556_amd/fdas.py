@@ -34,7 +34,7 @@ EXPORTED = (
     "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params", "fdas_prescreen_get_params",
     "fdas_prescreen_features", "fdas_prescreen_forward", "fdas_prescreen_infer", "fdas_prescreen_gradient",
     "fdas_prescreen_train_step", "fdas_search_blocks", "fdas_search_flagged", "fdas_block_closure",
-    "fdas_prescreen_init_params",
+    "fdas_prescreen_init_params", "fdas_harmonic_sum_noalloc",
 )
 
 
@@ -109,6 +109,7 @@ def lib():
     L.fdas_plan_destroy.argtypes = [vp]
     L.fdas_convolve.argtypes = [vp, vp, i64, vp, i64, vp]
     L.fdas_harmonic_sum.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp]
+    L.fdas_harmonic_sum_noalloc.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp]
     L.fdas_candidates.argtypes = [vp, vp, vp, vp, i64, ctypes.POINTER(i64), vp, vp]
     L.fdas_last_error.argtypes = []
     L.fdas_last_error.restype = ctypes.c_char_p
@@ -143,7 +144,8 @@ def lib():
                  "fdas_prescreen_create", "fdas_prescreen_destroy", "fdas_prescreen_set_params",
                  "fdas_prescreen_get_params", "fdas_prescreen_features", "fdas_prescreen_forward",
                  "fdas_prescreen_infer", "fdas_prescreen_gradient", "fdas_prescreen_train_step", "fdas_search_blocks",
-                 "fdas_search_flagged", "fdas_block_closure", "fdas_prescreen_init_params"):
+                 "fdas_search_flagged", "fdas_block_closure", "fdas_prescreen_init_params",
+                 "fdas_harmonic_sum_noalloc"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -247,6 +249,15 @@ def harmonic_sum(plan, fop, n, cands, counts, ta=None, ld=None, stream=None):
         ld = fop.shape[1]
     _check(lib().fdas_harmonic_sum(plan.handle, _ptr(fop), int(n), int(ld), _ptr(ta), _ptr(cands),
                                    _ptr(counts), _stream(stream)))
+
+
+def harmonic_sum_noalloc(plan, fop, n, cands, counts, ta=None, ld=None, stream=None):
+    """fdas_harmonic_sum with its scratch in the library's static device array
+    (allocates nothing; n <= 2^22; asynchronous)."""
+    if ld is None:
+        ld = fop.shape[1]
+    _check(lib().fdas_harmonic_sum_noalloc(plan.handle, _ptr(fop), int(n), int(ld), _ptr(ta), _ptr(cands),
+                                           _ptr(counts), _stream(stream)))
 
 
 def _pinned_out(plan, capacity):
