@@ -211,6 +211,8 @@ def bench_batch(args, torch, fdas, synth, dev):
         "config": {"workload": f"batch_{T}_trials", "trials": T, "lengths": sorted(set(lens)),
                    "total_bins": bins, "templates": 85, "harmonics": 8, "seeds": "3000+b",
                    "tuning": tuning},
+        "chosen_ols_chunk": tuning["ols_chunk"],
+        "chosen_hsum_tile_columns": tuning["hsum_tile"],
         "batch_gpu_ms_per_step": round(gpu_ms / args.steps, 3),
         "batch_hbm_gbs_algorithmic": round(hbm_bytes / (gpu_ms / args.steps * 1e-3) / 1e9, 1),
         "single_calls_ms_per_step": round(single_ms, 3),
@@ -223,38 +225,75 @@ def bench_batch(args, torch, fdas, synth, dev):
     print(json.dumps(out), flush=True)
 
 
+PRESCREEN_TEST_SEED0 = 6_000_000
+
+
+def _train_spectrum(args):
+    """Training spectrum i of the label recipe (run in a worker process)."""
+    from paper_1806_01556_amd import synth
+    i, r = args
+    return synth.make_spectrum(r["n"], r["seed0"] + i, n_random=i % 4, r_range=tuple(r["r_range"]),
+                               z_range=tuple(r["z_range"]), snr_range=tuple(r["snr_range"]),
+                               harm_range=tuple(r["harm_range"]))[0]
+
+
+def _test_spectrum(i):
+    """Test spectrum i: 2^22 bins, 1 + (i mod 3) pulsars with r ~ U[1e4, 2e6],
+    z ~ U[-42, 42], SNR ~ U[5, 20], 1-8 harmonics (worker process)."""
+    from paper_1806_01556_amd import synth
+    spec, pulsars = synth.make_spectrum(1 << 22, PRESCREEN_TEST_SEED0 + i, n_random=1 + i % 3, r_range=(1e4, 2e6),
+                                        snr_range=(5.0, 20.0))
+    return spec, [(p.r, p.z, p.snr, p.n_harm) for p in pulsars]
+
+
+def _spawn_map(fn, items, workers):
+    """fn over items in fresh worker processes (spawned: the parent has a GPU
+    context, which a forked child must not inherit), results in order."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(fn, items, chunksize=max(1, len(items) // (4 * workers))))
+
+
+def _keys(c):
+    """int64 key (harm, z + 64, r) of each candidate record, sorted."""
+    k = (c["harm"].astype(np.int64) << 40) | ((c["z"].astype(np.int64) + 64) << 32) | c["r"].astype(np.int64)
+    return np.sort(k)
+
+
 def bench_prescreen(args, torch, fdas, synth, dev):
-    """Learned block pre-screen: train on the oracle-labelled 2^16-bin spectra of
-    tests/golden/prescreen_labels.txt (regenerated from their seeds), pick the
-    logit threshold on held-out spectra, then search `trials` SKA-sized
-    spectra (2^22 bins, seeds 6e6 + i, 1-3 pulsars) on the flagged blocks and
-    their harmonic multiples, against the plain search of the same spectra.
-    Recall counts the plain search's significant candidates (power above
-    T_k at a per-cell false-alarm probability of 1e-12) that the pre-screened
-    search also reports."""
+    """Learned block pre-screen at the pre-screen workload's sizes: train on
+    10,000 oracle-labelled spectra (tests/golden/prescreen_labels.txt, 2^16
+    bins each, regenerated from their seeds; the 240 further labelled spectra
+    pick the logit threshold), then search 256 spectra of 2^22 bins on the
+    flagged blocks and their harmonic multiples, against the plain search of
+    the same spectra.  Recall is reported three ways: over every candidate
+    cell of the plain search at the configured p_fa (1e-6), over its
+    significant cells (power above T_k at a per-cell false-alarm probability
+    of 1e-12, cells a screen can be asked to keep), and per injected pulsar
+    the plain search detects."""
     path = os.path.join(ROOT, "tests", "golden", "prescreen_labels.txt")
     with open(path) as f:
         lines = f.read().splitlines()
     recipe = json.loads(next(l for l in lines if l.startswith("# recipe: "))[len("# recipe: "):])
     rows = [l.split() for l in lines if l and not l.startswith("#")]
+    nspec = len(rows)
     n_tr = recipe["n"]
     bpb = n_tr // 4096
+    workers = cpu_workers()
+    t_syn = time.perf_counter()
+    specs = _spawn_map(_train_spectrum, [(int(i), recipe) for i, _ in rows], workers)
+    t_syn = time.perf_counter() - t_syn
     ps = fdas.Prescreen(max_batch=1024)  # one inference call covers a 2^22-bin spectrum
-    nspec = len(rows)
     feats = torch.empty((nspec * bpb, 4096), dtype=torch.float32, device=dev)
     labels = torch.tensor([float(c) for _, bits in rows for c in bits], dtype=torch.float32, device=dev)
-    t_syn = time.perf_counter()
-    for k, (i, _) in enumerate(rows):
-        i = int(i)
-        spec = synth.make_spectrum(n_tr, recipe["seed0"] + i, n_random=i % 4, r_range=tuple(recipe["r_range"]),
-                                   z_range=tuple(recipe["z_range"]), snr_range=tuple(recipe["snr_range"]),
-                                   harm_range=tuple(recipe["harm_range"]))[0]
-        ps.features(torch.from_numpy(spec).to(dev), n_tr, np.arange(bpb), feats[k * bpb:(k + 1) * bpb])
+    for k, sp in enumerate(specs):
+        ps.features(torch.from_numpy(sp).to(dev), n_tr, bpb, feats[k * bpb:(k + 1) * bpb])
+    del specs
     torch.cuda.synchronize()
-    t_syn = time.perf_counter() - t_syn
-    n_val = max(1, nspec // 10)
-    tr = np.arange((nspec - n_val) * bpb)
-    va = np.arange((nspec - n_val) * bpb, nspec * bpb)
+    n_train = min(args.train_spectra, nspec - 1)
+    tr = np.arange(n_train * bpb)
+    va = np.arange(n_train * bpb, nspec * bpb)
     lab_np = labels.cpu().numpy()
     pos = float(lab_np[tr].sum())
     pos_weight = (tr.size - pos) / max(pos, 1.0)
@@ -274,8 +313,10 @@ def bench_prescreen(args, torch, fdas, synth, dev):
             idx = perm[s0:s0 + B]
             torch.index_select(feats, 0, idx, out=xb)
             torch.index_select(labels, 0, idx, out=yb)
-            ps.train_step(xb, yb, B, pos_weight, lr * (0.5 ** (ep // 5)), logit_b, loss)
+            ps.train_step(xb, yb, B, pos_weight, lr * (0.5 ** (ep // 4)), logit_b, loss)
             steps += 1
+        print(f"prescreen: epoch {ep + 1}/{args.epochs}, batch loss {float(loss.item()):.4f}", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     t_tr = time.perf_counter() - t_tr
     final_loss = float(loss.item())
@@ -289,72 +330,75 @@ def bench_prescreen(args, torch, fdas, synth, dev):
 
     lv = logits_of(feats[va[0]:va[-1] + 1], va.size).cpu().numpy()
     yv = lab_np[va]
-    # threshold: 99 % of the held-out positive blocks flagged, less a margin of 0.5
-    # (a few positives are single noise cells above the labelling threshold,
-    # which no screen can predict and which are not significant candidates)
-    thr = float(np.quantile(lv[yv > 0.5], 0.01) - 0.5) if (yv > 0.5).any() else 0.0
-    val_flag = float(np.mean(lv > thr))
-    val_recall = float(np.mean(lv[yv > 0.5] > thr)) if (yv > 0.5).any() else 1.0
+    del feats
+    # operating points from the held-out positive blocks' logits: the
+    # default flags blocks above their 5 % quantile, the others are looser
+    qs = [(f"val_q{int(100 * q)}", float(np.quantile(lv[yv > 0.5], q))) for q in (0.01, 0.05, 0.2, 0.5)]
+    val_flag = {name: round(float(np.mean(lv > th)), 4) for name, th in qs}
+    val_recall = {name: round(float(np.mean(lv[yv > 0.5] > th)), 4) for name, th in qs}
 
     # ---- test spectra -------------------------------------------------------
     n = 1 << 22
     nblk = n // 4096
+    T = args.test_spectra
+    t_syn2 = time.perf_counter()
+    test = _spawn_map(_test_spectrum, list(range(T)), workers)
+    t_syn2 = time.perf_counter() - t_syn2
+    xs = [torch.from_numpy(sp).to(dev) for sp, _ in test]
+    pulsars = [pl for _, pl in test]
+    del test
     plan = fdas.plan_create(n_max=n)
     fop = fdas.alloc_fop(plan, n, dev)
     cands, counts = fdas.alloc_cands(plan, dev)
-    tsig = fdas.thresholds(8, recipe["p_sig"])
+    tsig = fdas.thresholds(8, recipe["p_sig"]).astype(np.float32)
     lgt = torch.empty(nblk, dtype=torch.float32, device=dev)
+    rb_cap = plan.desc.n_harm * plan.desc.cand_capacity
 
     def significant(c):
-        keep = c["power"] > tsig[c["harm"] - 1]
-        return set(zip(c["harm"][keep].tolist(), c["z"][keep].tolist(), c["r"][keep].tolist()))
+        return c[c["power"] > tsig[c["harm"] - 1]]
 
-    # operating points: the held-out threshold, then looser screens
-    qs = [("val_p99", thr)] + [(f"val_q{int(100 * q)}", float(np.quantile(lv[yv > 0.5], q)))
-                               for q in (0.05, 0.2, 0.5)]
-    T = args.trials
-    stats = {name: {"ref": 0, "hit": 0, "pref": 0, "phit": 0, "t": 0.0, "flag": [], "search": []}
-             for name, _ in qs}
-    t_plain = 0.0
-    xs = []
+    stats = {name: {"all": 0, "all_hit": 0, "sig": 0, "sig_hit": 0, "pul": 0, "pul_hit": 0, "flag": [],
+                    "search": []} for name, _ in qs}
+    over = 0
     for ti in range(T):
-        spec, pulsars = synth.make_spectrum(n, 6_000_000 + ti, n_random=1 + ti % 3, r_range=(1e4, 2e6))
-        x = torch.from_numpy(spec).to(dev)
-        xs.append(x)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        x = xs[ti]
         fdas.convolve(plan, x, fop, n=n)
         fdas.harmonic_sum(plan, fop, n, cands, counts)
-        c_plain, _ = fdas.candidates(plan, cands, counts, allow_overflow=True)
-        t_plain += time.perf_counter() - t0
-        ref = significant(c_plain)
+        c_plain, hc = fdas.candidates(plan, cands, counts, capacity=rb_cap, allow_overflow=True)
+        over += int(np.any(hc > plan.desc.cand_capacity))
+        k_all, sig = _keys(c_plain), significant(c_plain)
+        k_sig = _keys(sig)
+        ps.infer(x, n, nblk, lgt)
+        lg = lgt.cpu().numpy()
         for name, th in qs:
             st = stats[name]
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ps.infer(x, n, nblk, lgt)  # features and network in one kernel
-            lg = lgt.cpu().numpy()
+            fdas.search_flagged(plan, x, n, fop, lgt, th, cands, counts)
+            c_pre, _ = fdas.candidates(plan, cands, counts, capacity=rb_cap, allow_overflow=True)
+            k_pre = _keys(c_pre)
+            st["all"] += k_all.size
+            st["all_hit"] += int(np.isin(k_all, k_pre, assume_unique=True).sum())
+            st["sig"] += k_sig.size
+            st["sig_hit"] += int(np.isin(k_sig, k_pre, assume_unique=True).sum())
             flagged = np.nonzero(lg > th)[0]
-            search = fdas.block_closure(flagged, n)
-            fdas.search_blocks(plan, x, n, fop, search, cands, counts)
-            c_pre, _ = fdas.candidates(plan, cands, counts, allow_overflow=True)
-            st["t"] += time.perf_counter() - t0
-            got = significant(c_pre)
-            st["ref"] += len(ref)
-            st["hit"] += len(ref & got)
             st["flag"].append(flagged.size / nblk)
-            st["search"].append(search.size / nblk)
-            for p in pulsars:
-                b0 = int(p.r) // 4096
-                if any(abs(r // 4096 - b0) <= 1 for _, _, r in ref):
-                    st["pref"] += 1
-                    st["phit"] += int(any(abs(r // 4096 - b0) <= 1 for _, _, r in (ref & got)))
-    # the same spectra with two in flight, as in the headline: two plans,
+            st["search"].append(fdas.block_closure(flagged, n).size / nblk)
+            got_blocks = set((c_pre["r"][c_pre["power"] > tsig[c_pre["harm"] - 1]] // 4096).tolist())
+            sig_blocks = set((sig["r"] // 4096).tolist())
+            for r0, _, _, _ in pulsars[ti]:
+                b0 = int(r0) // 4096
+                near = {b0 - 1, b0, b0 + 1}
+                if near & sig_blocks:  # the plain search detects this pulsar
+                    st["pul"] += 1
+                    st["pul_hit"] += int(bool(near & sig_blocks & got_blocks))
+        if (ti + 1) % 32 == 0:
+            print(f"prescreen: {ti + 1}/{T} test spectra compared", file=sys.stderr, flush=True)
+
+    # throughput with two spectra in flight, as in the headline: two plans,
     # pre-screens and streams; inference from the spectrum, device-side block
-    # selection (fdas_search_flagged) and search of spectrum k+1 are queued
-    # before the candidates of spectrum k are read back (DMA), at the default
-    # threshold, against the plain search run the same way
-    thr5 = dict(qs)["val_q5"]
+    # selection and search of spectrum k+1 are queued before the candidates of
+    # spectrum k are read back (DMA), at the default threshold, against the
+    # plain search run the same way, over the T test spectra
+    thr = dict(qs)["val_q5"]
     theta = ps.get_params()
     pss = [ps, fdas.Prescreen(max_batch=1)]  # inference from the spectrum needs no batch workspace
     pss[1].set_params(theta)
@@ -363,89 +407,84 @@ def bench_prescreen(args, torch, fdas, synth, dev):
     bufs2 = [(cands, counts), fdas.alloc_cands(plans2[1], dev)]
     lgs = [torch.empty(nblk, dtype=torch.float32, device=dev) for _ in range(2)]
     strs = [torch.cuda.current_stream(), torch.cuda.Stream()]
-    rb_cap = plan.desc.n_harm * plan.desc.cand_capacity
 
-    def pipe(steps, screened, check=False):
-        got = []
+    def pipe(steps, screened):
         for k in range(steps + 1):
             if k < steps:
                 i, xk = k % 2, xs[k % T]
                 st_ = strs[i]
                 if screened:
                     pss[i].infer(xk, n, nblk, lgs[i], stream=st_)
-                    fdas.search_flagged(plans2[i], xk, n, fops2[i], lgs[i], thr5, bufs2[i][0], bufs2[i][1],
+                    fdas.search_flagged(plans2[i], xk, n, fops2[i], lgs[i], thr, bufs2[i][0], bufs2[i][1],
                                         stream=st_)
                 else:
                     fdas.convolve(plans2[i], xk, fops2[i], n=n, stream=st_)
                     fdas.harmonic_sum(plans2[i], fops2[i], n, bufs2[i][0], bufs2[i][1], stream=st_)
             if k >= 1:
                 j = (k - 1) % 2
-                c, _ = fdas.candidates(plans2[j], bufs2[j][0], bufs2[j][1], capacity=rb_cap, stream=strs[j],
-                                       allow_overflow=True, copy=False)
-                if check:
-                    got.append(len(significant(c)))
-        return got
+                fdas.candidates(plans2[j], bufs2[j][0], bufs2[j][1], capacity=rb_cap, stream=strs[j],
+                                allow_overflow=True, copy=False)
 
-    # untimed pass over the T spectra: the significant cells found
-    sig_pre = pipe(T, True, check=True)
-    sig_plain = pipe(T, False, check=True)
+    pipe(4, True)
+    pipe(4, False)
     torch.cuda.synchronize()
-    reps = 4 * T
     t0 = time.perf_counter()
-    pipe(reps, True)
+    pipe(T, True)
     torch.cuda.synchronize()
-    t_pre2 = time.perf_counter() - t0
+    t_pre = time.perf_counter() - t0
     t0 = time.perf_counter()
-    pipe(reps, False)
+    pipe(T, False)
     torch.cuda.synchronize()
-    t_plain2 = time.perf_counter() - t0
-    pipelined = {"steps": reps, "prescreen_spectra_per_s": round(reps / t_pre2, 3),
-                 "plain_spectra_per_s": round(reps / t_plain2, 3),
-                 "speedup_vs_plain": round(t_plain2 / t_pre2, 3),
-                 "significant_cells_prescreen": int(sum(sig_pre)),
-                 "significant_cells_plain": int(sum(sig_plain)),
-                 "note": "default threshold; block selection on the device (fdas_search_flagged), "
-                         "readback of step k while step k+1 runs"}
+    t_plain = time.perf_counter() - t0
     pss[1].destroy()
     plans2[1].destroy()
 
     points = {}
     for name, th in qs:
         st = stats[name]
-        points[name] = {"logit_threshold": round(th, 4), "spectra_per_s": round(T / st["t"], 3),
-                        "speedup_vs_plain": round(t_plain / st["t"], 3),
-                        "recall_significant_cells": round(st["hit"] / max(st["ref"], 1), 5),
-                        "recall_pulsars": round(st["phit"] / max(st["pref"], 1), 5),
+        points[name] = {"logit_threshold": round(th, 4),
+                        "recall_all_cells": round(st["all_hit"] / max(st["all"], 1), 5),
+                        "recall_significant_cells": round(st["sig_hit"] / max(st["sig"], 1), 5),
+                        "recall_pulsars": round(st["pul_hit"] / max(st["pul"], 1), 5),
                         "flagged_block_fraction": round(float(np.mean(st["flag"])), 4),
-                        "searched_block_fraction": round(float(np.mean(st["search"])), 4)}
+                        "searched_block_fraction": round(float(np.mean(st["search"])), 4),
+                        "val_flagged_fraction": val_flag[name], "val_block_recall": val_recall[name]}
     head = points["val_q5"]
+    st5 = stats["val_q5"]
     out = {
         "metric": "FDAS spectra/s with the learned block pre-screen (2^22 pts, 85 templates, 8 harmonics)",
-        "value": head["spectra_per_s"],
+        "value": round(T / t_pre, 3),
         "unit": "spectra/s",
         "n_gpus": 1,
         "steps": T,
-        "warmup": 0,
-        "ms_per_step": round(1e3 / head["spectra_per_s"], 3),
+        "warmup": 4,
+        "ms_per_step": round(1e3 * t_pre / T, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32 search, bf16 network weights",
         "data": "synthetic",
-        "config": {"workload": "prescreen_2^22", "test_spectra": T, "train_spectra": nspec - n_val,
-                   "val_spectra": n_val, "train_n": n_tr, "epochs": args.epochs, "train_steps": steps,
-                   "pos_weight": round(pos_weight, 3), "p_label": recipe.get("p_label"), "p_sig": recipe["p_sig"]},
+        "config": {"workload": "prescreen_2^22", "test_spectra": T, "train_spectra": n_train,
+                   "val_spectra": nspec - n_train, "train_n": n_tr, "epochs": args.epochs, "train_steps": steps,
+                   "pos_weight": round(pos_weight, 3), "p_fa": 1e-6, "p_label": recipe.get("p_label"),
+                   "p_sig": recipe["p_sig"], "test_seeds": f"{PRESCREEN_TEST_SEED0}+i",
+                   "note": "training spectra have 2^16 bins instead of 2^20 (the FP64 oracle labels 10,240 of "
+                           "them in minutes; 2^20 would take about 14 CPU hours); the block statistics "
+                           "are the same"},
         "plain_spectra_per_s": round(T / t_plain, 3),
-        "pipelined": pipelined,
+        "speedup_vs_plain": round(t_plain / t_pre, 3),
+        "recall_all_cells": head["recall_all_cells"],
+        "recall_significant_cells": head["recall_significant_cells"],
+        "recall_pulsars": head["recall_pulsars"],
+        "plain_candidate_cells": st5["all"],
+        "plain_significant_cells": st5["sig"],
+        "pulsars_detected_by_plain": st5["pul"],
+        "spectra_with_list_overflow": over,
         "operating_point": "val_q5: flag blocks whose logit exceeds the 5 % quantile of the held-out "
-                           "positive blocks' logits",
-        "significant_cells": stats["val_q5"]["ref"],
-        "pulsars_detected_by_plain": stats["val_q5"]["pref"],
+                           "positive blocks' logits; throughput with two spectra in flight",
         "operating_points": points,
-        "val_flagged_fraction": round(val_flag, 4),
-        "val_block_recall": round(val_recall, 4),
         "train": {"final_batch_loss": round(final_loss, 5), "seconds": round(t_tr, 2),
-                  "synthesis_s": round(t_syn, 1)},
+                  "synthesis_s": round(t_syn, 1), "test_synthesis_s": round(t_syn2, 1), "workers": workers},
     }
     ps.destroy()
     plan.destroy()
@@ -477,7 +516,10 @@ def main():
                     help="ska: one 2^22-bin spectrum per step (the headline); batch: 64 dispersion trials of "
                          "uneven length per step through the batch calls; prescreen: train the learned block "
                          "pre-screen on oracle-labelled spectra, then search 2^22-bin spectra on flagged blocks")
-    ap.add_argument("--epochs", type=int, default=12, help="prescreen workload: training epochs")
+    ap.add_argument("--epochs", type=int, default=8, help="prescreen workload: training epochs")
+    ap.add_argument("--train-spectra", type=int, default=10000,
+                    help="prescreen workload: labelled spectra to train on (the rest pick the threshold)")
+    ap.add_argument("--test-spectra", type=int, default=256, help="prescreen workload: 2^22-bin test spectra")
     ap.add_argument("--trials", type=int, default=64, help="batch workload: trials per step")
     args = ap.parse_args()
 

@@ -97,7 +97,7 @@ typedef struct {
   fdas_conv_method method;
   fdas_precision precision;
   fdas_hsum_index hsum_index;
-  int32_t ols_chunk;     /* overlap-save FFT length C: 0 = default (4096); only 4096 is built */
+  int32_t ols_chunk;     /* overlap-save FFT length C: 2048, 4096 or 8192 (0 = 4096); C - (L_max - 1) >= 1024 */
   int32_t device;        /* HIP device ordinal */
 } fdas_plan_desc;
 
@@ -207,9 +207,11 @@ typedef struct {
 /* Launch parameters chosen by fdas_autotune (all fields 0 = built-in default). */
 typedef struct {
   int32_t conv_templates_per_item; /* at most this many templates share one forward FFT (1..2*z_max+1; 0 = all of a chunk's templates in a workgroup's range) */
-  int32_t conv_workgroups_per_cu;  /* resident convolution workgroups per compute unit (1..2) */
+  int32_t conv_waves_per_simd;     /* resident convolution waves per SIMD (1..2; default 2) */
   int32_t overlap_groups;          /* trial groups whose harmonic sums overlap later convolutions (1..8) */
   int32_t emit_workgroups;         /* workgroups of the candidate-emission pass (64..16384) */
+  int32_t ols_chunk;               /* overlap-save chunk length C of the batch (2048, 4096, 8192; 0 = the plan's) */
+  int32_t hsum_tile;               /* columns per harmonic-sum workgroup tile (256, 512, 1024; 0 = 1024) */
 } fdas_tuning;
 
 /* Convolution + harmonic sum (default thresholds) of `count` trials,
@@ -229,9 +231,14 @@ fdas_status fdas_candidates_batch(fdas_plan* plan, const fdas_trial* h_trials, i
                                   int64_t h_capacity, int64_t* h_offsets, int32_t* h_counts, void* stream);
 
 /* Time the batch path on these trials (their buffers are overwritten) over a
- * set of launch parameters, keep the fastest in the plan for later batch
+ * set of launch parameters -- the overlap-save chunk length C (the N_OLS-FT
+ * of Section 2.1.2), the convolution's waves per SIMD and templates per
+ * forward FFT, the harmonic-sum tile width, the overlap groups (Section 3.3)
+ * and the emission grid -- keep the fastest in the plan for later batch
  * calls, and report it in *out (optional).  `repeats` timed runs per
- * setting (>= 1).  Synchronises. */
+ * setting (>= 1).  Results do not depend on the setting (every chunk length
+ * computes the same correlation within FP32 rounding; candidates differ only
+ * where a sum lies within rounding of its threshold).  Synchronises. */
 fdas_status fdas_autotune(fdas_plan* plan, const fdas_trial* h_trials, int32_t count, int32_t repeats,
                           fdas_tuning* out, void* stream);
 

@@ -127,10 +127,9 @@ hipError_t ensure_tables(fdas_plan* p, int count, size_t stage_bytes) {
   return hipSuccess;
 }
 
-int cu_count(const fdas_plan* p) { return std::max(1, p->conv_slots / 2); }
-
 struct Launch {
-  int tpg = 0, slots = 0, groups = 1, eblocks = 1024;
+  const OlsTables* ols = nullptr;          // chunk length of the convolution
+  int tpg = 0, slots = 0, groups = 1, eblocks = 1024, cols = 1024;
   std::vector<int> tlo, thi;               // trials of each group
   std::vector<int64_t> ilo, ihi;           // convolution items of each group
   std::vector<int> blo, bhi;               // harmonic-sum workgroups of each group
@@ -140,8 +139,14 @@ struct Launch {
 // Per-trial table entries and the group split.
 fdas_status plan_launch(fdas_plan* p, const fdas_trial* t, int count, Launch& L, ConvTrial* ct, HsTrial* ht) {
   const int rows = p->rows;
-  const int V = p->geom.V;
-  L.slots = p->tuning.conv_workgroups_per_cu > 0 ? p->tuning.conv_workgroups_per_cu * cu_count(p) : p->conv_slots;
+  const int C = p->tuning.ols_chunk > 0 ? p->tuning.ols_chunk : p->ols[p->ols_idx].geom.C;
+  hipError_t e0 = ols_tables(p, C, &L.ols);
+  if (e0 != hipSuccess) return hip_fail(e0, "building the overlap-save tables of the batch's chunk length");
+  const int V = L.ols->geom.V;
+  // waves per SIMD -> workgroups per compute unit (4 SIMDs, C/16 threads per workgroup)
+  const int wps = p->tuning.conv_waves_per_simd > 0 ? p->tuning.conv_waves_per_simd : 2;
+  L.slots = p->cus * std::max(1, 4 * wps * 64 / ols_threads(C));
+  L.cols = p->tuning.hsum_tile > 0 ? p->tuning.hsum_tile : 1024;
   // 0: every workgroup's range of (chunk, template) pairs shares one forward
   // FFT per chunk it touches
   L.tpg = p->tuning.conv_templates_per_item > 0 ? std::min(rows, p->tuning.conv_templates_per_item) : 0;
@@ -151,7 +156,7 @@ fdas_status plan_launch(fdas_plan* p, const fdas_trial* t, int count, Launch& L,
   for (int i = 0; i < count; ++i) {
     const int* order = nullptr;
     int nblocks = 0;
-    hipError_t e = tile_order_for(p, t[i].n, &order, &nblocks);
+    hipError_t e = tile_order_for(p, t[i].n, &order, &nblocks, L.cols);
     if (e != hipSuccess) return hip_fail(e, "uploading a harmonic-sum tile order");
     ct[i] = ConvTrial{static_cast<const float2*>(t[i].d_spectrum), t[i].d_fop, t[i].n, t[i].ld, item};
     ht[i] = HsTrial{t[i].d_fop, t[i].ld, t[i].d_cands, t[i].d_counts, order, (int)t[i].n, block, nblocks, 0};
@@ -196,13 +201,12 @@ hipError_t record_sequence(fdas_plan* p, int count, const Launch& L) {
   hipStream_t cs = p->cap_stream, ss = p->side_stream;
   hipError_t e = launch_zero_counts_batch(p->d_hs_trials, count, p->desc.n_harm, cs);
   for (int g = 0; g < L.groups && e == hipSuccess; ++g) {
-    e = launch_ols_conv_batch(p->d_conv_trials, count, L.ilo[g], L.ihi[g], p->d_H, p->d_tw1, p->d_tw2, p->rows,
-                              L.tpg, p->geom, L.slots, cs);
+    e = launch_ols_conv_batch(p->d_conv_trials, count, L.ilo[g], L.ihi[g], *L.ols, p->rows, L.tpg, L.slots, cs);
     if (e == hipSuccess) e = hipEventRecord(p->fork_events[g], cs);
     if (e == hipSuccess) e = hipStreamWaitEvent(ss, p->fork_events[g], 0);
     if (e == hipSuccess)
       e = launch_harmsum_batch85(p->d_hs_trials, count, L.blo[g], L.bhi[g], p->desc.n_harm, p->d_ta,
-                                 p->desc.cand_capacity, p->d_bhitrows, p->d_bhitrow_count, L.eblocks, ss);
+                                 p->desc.cand_capacity, p->d_bhitrows, p->d_bhitrow_count, L.eblocks, L.cols, ss);
   }
   if (e == hipSuccess) e = hipEventRecord(p->fork_events[kMaxGroups], ss);
   if (e == hipSuccess) e = hipStreamWaitEvent(cs, p->fork_events[kMaxGroups], 0);
@@ -252,7 +256,7 @@ fdas_status search_batch(fdas_plan* p, const fdas_trial* t, int count, hipStream
       (e = hipMemcpyAsync(p->d_hs_trials, ht, count * sizeof(HsTrial), hipMemcpyHostToDevice, s)) != hipSuccess ||
       (e = hipEventRecord(p->stage_done, s)) != hipSuccess)
     return hip_fail(e, "uploading the batch tables");
-  std::vector<int64_t> key = {count, L.tpg, L.slots, L.groups, L.eblocks, p->desc.n_harm,
+  std::vector<int64_t> key = {count, L.tpg, L.slots, L.groups, L.eblocks, p->desc.n_harm, L.ols->geom.C, L.cols,
                               (int64_t)(uintptr_t)p->d_conv_trials, (int64_t)(uintptr_t)p->d_hs_trials,
                               (int64_t)(uintptr_t)p->d_bhitrows};
   for (int g = 0; g < L.groups; ++g) {
@@ -443,8 +447,14 @@ fdas_status fdas_set_tuning(fdas_plan* p, const fdas_tuning* t) {
     v = *t;
     if (v.conv_templates_per_item < 0 || v.conv_templates_per_item > p->rows)
       return fail(FDAS_ERR_INVALID_ARG, "conv_templates_per_item %d outside [0, %d]", v.conv_templates_per_item, p->rows);
-    if (v.conv_workgroups_per_cu < 0 || v.conv_workgroups_per_cu > 2)
-      return fail(FDAS_ERR_INVALID_ARG, "conv_workgroups_per_cu %d outside [0, 2]", v.conv_workgroups_per_cu);
+    if (v.conv_waves_per_simd < 0 || v.conv_waves_per_simd > 2)
+      return fail(FDAS_ERR_INVALID_ARG, "conv_waves_per_simd %d outside [0, 2]", v.conv_waves_per_simd);
+    if (v.ols_chunk != 0 && !ols_chunk_built(v.ols_chunk))
+      return fail(FDAS_ERR_UNSUPPORTED, "ols_chunk %d: the built chunk lengths are 2048, 4096 and 8192", v.ols_chunk);
+    if (v.ols_chunk != 0 && v.ols_chunk - (p->L_max - 1) < 1024)
+      return fail(FDAS_ERR_INVALID_ARG, "ols_chunk %d leaves fewer than 1024 valid outputs", v.ols_chunk);
+    if (v.hsum_tile != 0 && !harmsum_tile_built(v.hsum_tile))
+      return fail(FDAS_ERR_UNSUPPORTED, "hsum_tile %d: the built tile widths are 256, 512 and 1024", v.hsum_tile);
     if (v.overlap_groups < 0 || v.overlap_groups > kMaxGroups)
       return fail(FDAS_ERR_INVALID_ARG, "overlap_groups %d outside [0, %d]", v.overlap_groups, kMaxGroups);
     if (v.emit_workgroups != 0 && (v.emit_workgroups < 64 || v.emit_workgroups > 16384))
@@ -496,20 +506,39 @@ fdas_status fdas_autotune(fdas_plan* p, const fdas_trial* h_trials, int32_t coun
     }
     return r;
   };
-  // 1. templates per forward FFT x resident workgroups, no overlap
-  std::vector<int> tpgs = {0, 5, 9, 17, 29, 43};
-  for (int tpg : tpgs) {
-    if (tpg > p->rows) continue;
-    for (int wg : {1, 2}) {
+  // 1. chunk length x waves per SIMD (one forward FFT per chunk a workgroup's
+  //    range touches, no overlap); the chunk lengths whose overlap leaves
+  //    fewer than 1024 valid outputs are skipped
+  for (int C : {2048, 4096, 8192}) {
+    if (C - (p->L_max - 1) < 1024) continue;
+    for (int wps : {1, 2}) {
       fdas_tuning c{};
-      c.conv_templates_per_item = tpg;
-      c.conv_workgroups_per_cu = wg;
+      c.ols_chunk = C;
+      c.conv_waves_per_simd = wps;
       c.overlap_groups = 1;
       if ((st = consider(c)) != FDAS_OK) break;
     }
     if (st != FDAS_OK) break;
   }
-  // 2. overlap groups, 3. emission workgroups
+  // 2. templates per forward FFT, 3. harmonic-sum tile width
+  if (st == FDAS_OK) {
+    const fdas_tuning base = best;
+    for (int tpg : {5, 9, 17, 29, 43}) {
+      if (tpg > p->rows) continue;
+      fdas_tuning c = base;
+      c.conv_templates_per_item = tpg;
+      if ((st = consider(c)) != FDAS_OK) break;
+    }
+  }
+  if (st == FDAS_OK && graphable(p)) {
+    const fdas_tuning base = best;
+    for (int cols : {256, 512}) {
+      fdas_tuning c = base;
+      c.hsum_tile = cols;
+      if ((st = consider(c)) != FDAS_OK) break;
+    }
+  }
+  // 4. overlap groups, 5. emission workgroups
   if (st == FDAS_OK && graphable(p)) {
     const fdas_tuning base = best;
     for (int g : {2, 4, 8}) {
@@ -525,6 +554,14 @@ fdas_status fdas_autotune(fdas_plan* p, const fdas_trial* h_trials, int32_t coun
       c.emit_workgroups = eb;
       st = consider(c);
     }
+  }
+  if (st == FDAS_OK) {
+    // report the values the defaults stand for
+    if (best.ols_chunk == 0) best.ols_chunk = p->ols[p->ols_idx].geom.C;
+    if (best.conv_waves_per_simd == 0) best.conv_waves_per_simd = 2;
+    if (best.hsum_tile == 0) best.hsum_tile = 1024;
+    if (best.overlap_groups == 0) best.overlap_groups = 1;
+    if (best.emit_workgroups == 0) best.emit_workgroups = 1024;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -44,9 +44,11 @@ void free_plan(fdas_plan* p) {
   if (p->d_tscale) (void)hipFree(p->d_tscale);
   if (p->d_dtiles) (void)hipFree(p->d_dtiles);
   if (p->d_drows) (void)hipFree(p->d_drows);
-  if (p->d_H) (void)hipFree(p->d_H);
-  if (p->d_tw1) (void)hipFree(p->d_tw1);
-  if (p->d_tw2) (void)hipFree(p->d_tw2);
+  for (auto& t : p->ols) {
+    if (t.H) (void)hipFree(t.H);
+    if (t.tw1) (void)hipFree(t.tw1);
+    if (t.tw2) (void)hipFree(t.tw2);
+  }
   if (p->d_ta) (void)hipFree(p->d_ta);
   if (p->d_sort_a) (void)hipFree(p->d_sort_a);
   if (p->d_sort_b) (void)hipFree(p->d_sort_b);
@@ -128,11 +130,42 @@ void* noalloc_scratch(int device) {
   return g_scratch_ptr[device];
 }
 
-hipError_t tile_order_for(fdas_plan* p, int64_t n, const int** d_order, int* blocks) {
-  auto it = p->tile_orders.find(n);
+hipError_t ols_tables(fdas_plan* p, int C, const OlsTables** out) {
+  const int idx = ols_index(C);
+  if (idx < 0 || !ols_chunk_built(C)) return hipErrorInvalidValue;
+  OlsTables& t = p->ols[idx];
+  if (!t.H) {
+    std::vector<std::vector<std::complex<double>>> bank;
+    template_bank(p->desc.z_max, bank);
+    OlsGeom g{C, p->L_max / 2, C - (p->L_max - 1)};
+    std::vector<float> H, tw1, tw2;
+    ols_spectra(bank, g.C, g.P, H);
+    fft_twiddles(C, tw1, tw2);
+    float2 *dH = nullptr, *d1 = nullptr, *d2 = nullptr;
+    hipError_t e;
+    if ((e = upload(&dH, H.data(), H.size() * sizeof(float))) != hipSuccess ||
+        (e = upload(&d1, tw1.data(), tw1.size() * sizeof(float))) != hipSuccess ||
+        (e = upload(&d2, tw2.data(), tw2.size() * sizeof(float))) != hipSuccess) {
+      if (dH) (void)hipFree(dH);
+      if (d1) (void)hipFree(d1);
+      if (d2) (void)hipFree(d2);
+      return e;
+    }
+    t.geom = g;
+    t.H = dH;
+    t.tw1 = d1;
+    t.tw2 = d2;
+  }
+  *out = &t;
+  return hipSuccess;
+}
+
+hipError_t tile_order_for(fdas_plan* p, int64_t n, const int** d_order, int* blocks, int cols) {
+  const auto key = std::make_pair(n, cols);
+  auto it = p->tile_orders.find(key);
   if (it == p->tile_orders.end()) {
     std::vector<int> order;
-    harmsum_tile_order(n, order);
+    harmsum_tile_order(n, order, cols);
     int* d = nullptr;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&d), order.size() * sizeof(int));
     if (e == hipSuccess) e = hipMemcpy(d, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -140,7 +173,7 @@ hipError_t tile_order_for(fdas_plan* p, int64_t n, const int** d_order, int* blo
       if (d) (void)hipFree(d);
       return e;
     }
-    it = p->tile_orders.emplace(n, std::make_pair(d, (int)order.size())).first;
+    it = p->tile_orders.emplace(key, std::make_pair(d, (int)order.size())).first;
   }
   *d_order = it->second.first;
   *blocks = it->second.second;
@@ -225,8 +258,12 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   if (desc->hsum_index != FDAS_HSUM_STRETCH && desc->hsum_index != FDAS_HSUM_FUNDAMENTAL &&
       desc->hsum_index != FDAS_HSUM_HIGHEST)
     return fail(FDAS_ERR_INVALID_ARG, "unknown hsum_index %d", (int)desc->hsum_index);
-  if (desc->ols_chunk != 0 && desc->ols_chunk != fdas::kOlsC)
-    return fail(FDAS_ERR_UNSUPPORTED, "ols_chunk %d: only %d is built", (int)desc->ols_chunk, fdas::kOlsC);
+  if (desc->ols_chunk != 0 && !fdas::ols_chunk_built(desc->ols_chunk))
+    return fail(FDAS_ERR_UNSUPPORTED, "ols_chunk %d: the built chunk lengths are 2048, 4096 and 8192",
+                (int)desc->ols_chunk);
+  if (desc->ols_chunk != 0 && desc->ols_chunk - (fdas::tap_count(desc->z_max) - 1) < 1024)
+    return fail(FDAS_ERR_INVALID_ARG, "ols_chunk %d leaves fewer than 1024 valid outputs for %d-tap templates",
+                (int)desc->ols_chunk, fdas::tap_count(desc->z_max));
 
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
@@ -240,9 +277,7 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   p->device = desc->device;
   p->rows = 2 * desc->z_max + 1;
   p->L_max = fdas::tap_count(desc->z_max);
-  p->geom.C = fdas::kOlsC;
-  p->geom.P = p->L_max / 2;
-  p->geom.V = p->geom.C - (p->L_max - 1);
+  p->ols_idx = fdas::ols_index(desc->ols_chunk != 0 ? desc->ols_chunk : fdas::kOlsC);
 
   DeviceGuard dg(p->device);
   if (dg.err != hipSuccess) {
@@ -252,7 +287,7 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess && cus > 0)
-      p->conv_slots = 2 * cus;
+      p->cus = cus;
   }
   if ((e = fdas::resolve_noalloc_scratch(p->device)) != hipSuccess) {
     free_plan(p);
@@ -262,7 +297,7 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   std::vector<std::vector<std::complex<double>>> bank;
   fdas::template_bank(desc->z_max, bank);
   p->direct = desc->method == FDAS_CONV_DIRECT_MFMA;
-  std::vector<float> H, tw1, tw2, Bpk, tscale;
+  std::vector<float> Bpk, tscale;
   std::vector<uint16_t> Bsp;
   std::vector<int> dtiles, drows;
   if (p->direct && desc->precision != FDAS_PREC_FP32) {
@@ -272,9 +307,6 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
   } else if (p->direct) {
     fdas::direct_pack(bank, desc->z_max, Bpk, dtiles, drows, &p->dP_max, &p->dP8_max);
     p->dtiles = (int)dtiles.size() / 4;
-  } else {
-    fdas::ols_spectra(bank, p->geom.C, p->geom.P, H);
-    fdas::fft_twiddles(tw1, tw2);
   }
   p->h_ta.resize((size_t)desc->n_harm * p->rows);
   for (int k = 1; k <= desc->n_harm; ++k) {
@@ -297,11 +329,12 @@ fdas_status fdas_plan_create(const fdas_plan_desc* desc, fdas_plan** out) {
       free_plan(p);
       return hip_fail(e, "uploading the direct-method template operand");
     }
-  } else if ((e = upload(&p->d_H, H.data(), H.size() * sizeof(float))) != hipSuccess ||
-             (e = upload(&p->d_tw1, tw1.data(), tw1.size() * sizeof(float))) != hipSuccess ||
-             (e = upload(&p->d_tw2, tw2.data(), tw2.size() * sizeof(float))) != hipSuccess) {
-    free_plan(p);
-    return hip_fail(e, "uploading the overlap-save template spectra");
+  } else {
+    const fdas::OlsTables* t = nullptr;
+    if ((e = fdas::ols_tables(p, desc->ols_chunk ? desc->ols_chunk : fdas::kOlsC, &t)) != hipSuccess) {
+      free_plan(p);
+      return hip_fail(e, "uploading the overlap-save template spectra");
+    }
   }
   if ((e = upload(&p->d_ta, p->h_ta.data(), p->h_ta.size() * sizeof(float))) != hipSuccess) {
     free_plan(p);
@@ -358,8 +391,9 @@ fdas_status fdas_convolve(fdas_plan* p, const void* d_spectrum, int64_t n, float
                                          p->desc.precision == FDAS_PREC_SPLIT_BF16, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "launching the direct correlation");
   } else {
-    e = fdas::launch_ols_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2,
-                              p->rows, p->geom, p->conv_slots, static_cast<hipStream_t>(stream));
+    const fdas::OlsTables& t = p->ols[p->ols_idx];
+    e = fdas::launch_ols_conv(static_cast<const float2*>(d_spectrum), n, d_fop, ld, t, p->rows,
+                              fdas::ols_slots(p, t.geom.C), static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "launching the overlap-save convolution");
   }
   return ok();

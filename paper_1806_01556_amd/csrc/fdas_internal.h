@@ -18,7 +18,6 @@ void template_taps(int z, std::vector<std::complex<double>>& h);
 void template_bank(int z_max, std::vector<std::vector<std::complex<double>>>& bank);
 void ols_spectra(const std::vector<std::vector<std::complex<double>>>& bank, int C, int P,
                  std::vector<float>& out);
-void fft_twiddles(std::vector<float>& tw1, std::vector<float>& tw2);
 double erlang_threshold(int k, double p_fa);
 
 // Packed template operand of the direct (matrix-core) correlation: templates
@@ -30,8 +29,7 @@ void direct_pack(const std::vector<std::vector<std::complex<double>>>& bank, int
                  std::vector<int>& tiles, std::vector<int>& rows, int* P_max, int* P8_max);
 
 // ---- overlap-save geometry -------------------------------------------------
-constexpr int kOlsC = 4096;      // FFT length of one chunk
-constexpr int kOlsThreads = 256; // threads per workgroup (16 points each)
+constexpr int kOlsC = 4096;      // default FFT length of one chunk
 
 struct OlsGeom {
   int C;   // chunk FFT length
@@ -39,19 +37,34 @@ struct OlsGeom {
   int V;   // valid outputs per chunk = C - (L_max - 1)
 };
 
+// Device tables of one chunk length: template spectra [rows][C] and twiddles
+// (tw1 [16][C/16] = w_C^(k t); tw2 [17][TW2] = w_M^(k c), M = C/16, TW2 = M/16,
+// and in row 16 w32^p for the 8192-point transform).
+struct OlsTables {
+  OlsGeom geom{};
+  float2* H = nullptr;
+  float2* tw1 = nullptr;
+  float2* tw2 = nullptr;
+};
+
+bool ols_chunk_built(int C);  // 2048, 4096, 8192
+int ols_threads(int C);       // threads of a convolution workgroup (C / 16)
+int ols_slots_per_cu(int C);  // resident convolution workgroups per compute unit
+void fft_twiddles(int C, std::vector<float>& tw1, std::vector<float>& tw2);
+
 // ---- kernel launchers (k_*.hip) -------------------------------------------
-// slots: workgroups resident at once (2 per compute unit).
-hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld,
-                           const float2* H, const float2* tw1, const float2* tw2,
-                           int rows, const OlsGeom& g, int slots, hipStream_t s);
+// slots: workgroups of the persistent grid (all resident at once).
+hipError_t launch_ols_conv(const float2* x, int64_t n, float* fop, int64_t ld, const OlsTables& t, int rows,
+                           int slots, hipStream_t s);
 
 // Only the listed overlap-save chunks (chunk_list[0 .. nlist), device array)
-// and templates (FOP rows) z0 .. z0 + nr - 1.  With d_nlist the kernel reads
+// and templates (FOP rows) z0 .. z0 + nr - 1; zrow is the row of the
+// zero-drift template (written as |X|^2).  With d_nlist the kernel reads
 // the list length from device memory and nlist is only its upper bound (the
 // grid is sized for it).
-hipError_t launch_ols_conv_list(const float2* x, int64_t n, float* fop, int64_t ld, const float2* H,
-                                const float2* tw1, const float2* tw2, int z0, int nr, const OlsGeom& g, int slots,
-                                const int* chunk_list, int nlist, hipStream_t s, const int* d_nlist = nullptr);
+hipError_t launch_ols_conv_list(const float2* x, int64_t n, float* fop, int64_t ld, const OlsTables& t, int z0,
+                                int nr, int zrow, int slots, const int* chunk_list, int nlist, hipStream_t s,
+                                const int* d_nlist = nullptr);
 
 // FOP rows the stretched harmonic sums read as sources (k = 2 .. nh) of an
 // 2*Z+1-row plane: [*lo, *hi]; empty (lo > hi) when nh < 2.
@@ -70,8 +83,7 @@ struct ConvTrial {
 // contiguous ranges over the resident workgroups; at most tmax templates share
 // one forward FFT (0: a whole chunk's templates).
 hipError_t launch_ols_conv_batch(const ConvTrial* trials, int ntrials, int64_t item_begin, int64_t item_end,
-                                 const float2* H, const float2* tw1, const float2* tw2, int rows, int tmax,
-                                 const OlsGeom& g, int slots, hipStream_t s);
+                                 const OlsTables& t, int rows, int tmax, int slots, hipStream_t s);
 
 // Split 16-bit form of the packed operand: templates ordered and tiled as in
 // direct_pack; tile g covers 2 P8 taps in P8/8 groups of 16, each group 64
@@ -104,9 +116,11 @@ hipError_t launch_direct_conv_split(const float2* x, int64_t n, float* fop, int6
 // Columns handled by one workgroup of the 85-row harmonic-sum kernel.
 int harmsum_tile_columns();
 
-// Order in which the 85-row harmonic-sum kernel visits its column tiles:
-// tile_of_block[b] is the tile of workgroup b (-1: none), `blocks` entries.
-void harmsum_tile_order(int64_t n, std::vector<int>& tile_of_block);
+// Order in which the 85-row harmonic-sum kernel visits its column tiles of
+// `cols` columns: tile_of_block[b] is the tile of workgroup b (-1: none).
+void harmsum_tile_order(int64_t n, std::vector<int>& tile_of_block, int cols);
+// Tile widths (columns) the 85-row batch harmonic sum is built for: 256, 512, 1024.
+bool harmsum_tile_built(int cols);
 
 // Workspace of the two-phase 85-row harmonic sum.
 struct HsWork {
@@ -133,10 +147,11 @@ struct HsTrial {
 hipError_t launch_zero_counts_batch(const HsTrial* trials, int ntrials, int nh, hipStream_t s);
 
 // Two-phase 85-row stretch sum over phase-1 workgroups [blk_begin, blk_end)
-// of a batch (default thresholds ta, capacity cap per plane).
+// of a batch (default thresholds ta, capacity cap per plane), column tiles of
+// tile_cols columns (each trial's tile order built for that width).
 hipError_t launch_harmsum_batch85(const HsTrial* trials, int ntrials, int blk_begin, int blk_end, int n_harm,
                                   const float* ta, int cap, int4* hitrows, int32_t* hitrow_count, int eblocks,
-                                  hipStream_t s);
+                                  int tile_cols, hipStream_t s);
 
 // index: FDAS_HSUM_* (the stretch map uses the two-phase kernels for 85 rows).
 // counts[0 .. n_harm) are reset by the launch.

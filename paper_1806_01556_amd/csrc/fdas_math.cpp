@@ -286,22 +286,30 @@ void direct_pack_split(const std::vector<std::vector<cd>>& bank, int z_max, bool
   }
 }
 
-void fft_twiddles(std::vector<float>& tw1, std::vector<float>& tw2) {
-  // tw1[nb][t] = e^{+2 pi i nb t / 4096} (nb < 16, t < 256); tw2[q][c] = e^{+2 pi i q c / 256}.
-  tw1.assign(16 * 256 * 2, 0.0f);
-  tw2.assign(16 * 16 * 2, 0.0f);
+void fft_twiddles(int C, std::vector<float>& tw1, std::vector<float>& tw2) {
+  // tw1[nb][t] = e^{+2 pi i nb t / C} (nb < 16, t < C/16);
+  // tw2[q][c] = e^{+2 pi i q c / M} (q < 16, c < M/16, M = C/16);
+  // tw2[16][p] = e^{+2 pi i p / 32} (p < 16; used by the 8192-point transform)
+  const int NT = C / 16, M = C / 16, TW2 = M / 16;
+  tw1.assign((size_t)16 * NT * 2, 0.0f);
+  tw2.assign((size_t)17 * TW2 * 2, 0.0f);
   for (int nb = 0; nb < 16; ++nb)
-    for (int t = 0; t < 256; ++t) {
-      const cd w = expi2pi((double)(nb * t) / 4096.0);
-      tw1[(nb * 256 + t) * 2 + 0] = (float)w.real();
-      tw1[(nb * 256 + t) * 2 + 1] = (float)w.imag();
+    for (int t = 0; t < NT; ++t) {
+      const cd w = expi2pi((double)((long long)nb * t % C) / C);
+      tw1[((size_t)nb * NT + t) * 2 + 0] = (float)w.real();
+      tw1[((size_t)nb * NT + t) * 2 + 1] = (float)w.imag();
     }
   for (int q = 0; q < 16; ++q)
-    for (int c = 0; c < 16; ++c) {
-      const cd w = expi2pi((double)(q * c) / 256.0);
-      tw2[(q * 16 + c) * 2 + 0] = (float)w.real();
-      tw2[(q * 16 + c) * 2 + 1] = (float)w.imag();
+    for (int c = 0; c < TW2; ++c) {
+      const cd w = expi2pi((double)(q * c % M) / M);
+      tw2[((size_t)q * TW2 + c) * 2 + 0] = (float)w.real();
+      tw2[((size_t)q * TW2 + c) * 2 + 1] = (float)w.imag();
     }
+  for (int p = 0; p < 16 && p < TW2; ++p) {
+    const cd w = expi2pi((double)p / 32.0);
+    tw2[((size_t)16 * TW2 + p) * 2 + 0] = (float)w.real();
+    tw2[((size_t)16 * TW2 + p) * 2 + 1] = (float)w.imag();
+  }
 }
 
 static double log_survival(int k, double t) {
@@ -359,8 +367,7 @@ void stretch_source_rows(int Z, int nh, int* lo, int* hi) {
 // 8t(+7) next to each other, so a tile's k = 2, 4, 8 sources were read moments
 // before.  The sorted list is split into 8 contiguous segments, one per XCD
 // (workgroup b runs on XCD b mod 8), so a chain also shares one L2.
-void harmsum_tile_order(int64_t n, std::vector<int>& tile_of_block) {
-  const int64_t cols = harmsum_tile_columns();
+void harmsum_tile_order(int64_t n, std::vector<int>& tile_of_block, int cols) {
   const int T = (int)((n + cols - 1) / cols);
   int top = 0;
   while ((1LL << (top + 1)) <= (int64_t)std::max(1, T - 1)) ++top;  // octave of the largest tile index

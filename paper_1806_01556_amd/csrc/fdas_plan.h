@@ -13,8 +13,9 @@ struct fdas_plan {
   int device = 0;
   int rows = 0;          // 2*z_max + 1
   int L_max = 0;         // taps of the longest template
-  fdas::OlsGeom geom{};  // overlap-save chunk geometry
-  int conv_slots = 512;  // resident convolution workgroups (2 per compute unit)
+  int cus = 256;         // compute units of the device
+  fdas::OlsTables ols[3];  // overlap-save tables per chunk length 2048, 4096, 8192 (built on demand)
+  int ols_idx = 1;         // chunk length of the single-spectrum calls (the descriptor's)
   bool direct = false;      // FDAS_CONV_DIRECT_MFMA: matrix-core correlation instead of overlap-save
   float* d_Bpk = nullptr;   // direct: packed template operand
   int4* d_dtiles = nullptr; // direct: per-tile {P, first pair, members, 0}
@@ -22,9 +23,6 @@ struct fdas_plan {
   int dtiles = 0, dP_max = 0, dP8_max = 0;
   uint4* d_Bsp = nullptr;   // direct, split precisions: hi/lo 16-bit operand
   float* d_tscale = nullptr;  // direct, split precisions: per-tile 2^-eh
-  float2* d_H = nullptr;    // [rows][C] template spectra
-  float2* d_tw1 = nullptr;  // [16][256]
-  float2* d_tw2 = nullptr;  // [16][16]
   float* d_ta = nullptr;    // [n_harm][rows] default thresholds
   std::vector<float> h_ta;
   fdas_cand* d_sort_a = nullptr;  // [n_harm * cand_capacity] packed candidates
@@ -35,7 +33,7 @@ struct fdas_plan {
   fdas_cand* h_result = nullptr;  // page-locked result records of fdas_candidates_mapped
   int32_t* h_result_counts = nullptr;
   int bits_r = 1;                 // bits of the column index in the sort key
-  std::map<int64_t, std::pair<int*, int>> tile_orders;  // n -> (device tile order, workgroups)
+  std::map<std::pair<int64_t, int>, std::pair<int*, int>> tile_orders;  // (n, tile columns) -> (device order, workgroups)
   int4* d_hitrows = nullptr;      // [ceil(n_max/4)] rows with hits (harmonic sum phase 1)
   int32_t* d_hitrow_count = nullptr;
   fdas_tuning tuning{};           // batch launch parameters (0 = default)
@@ -78,12 +76,20 @@ fdas_status ok();
 fdas_status hip_fail(hipError_t e, const char* what);
 fdas_status check_fop_args(const fdas_plan* p, const void* fop, int64_t n, int64_t ld);
 // device tile order of the 85-row harmonic sum for length n (cached in the plan)
-hipError_t tile_order_for(fdas_plan* p, int64_t n, const int** d_order, int* blocks);
+hipError_t tile_order_for(fdas_plan* p, int64_t n, const int** d_order, int* blocks, int cols = 1024);
 // paper mode: planes [off[k], off[k+1]) of `sorted` reduced to their top_k
 // powers, appended to keep in (harm, z, r) order
 void keep_top_k(const fdas_cand* sorted, const int* off, int nh, int top_k, std::vector<fdas_cand>& keep);
 // release the batch-path resources of a plan
 void free_batch(fdas_plan* p);
+
+// Index of a chunk length in fdas_plan::ols (-1: not built).
+inline int ols_index(int C) { return C == 2048 ? 0 : (C == 4096 ? 1 : (C == 8192 ? 2 : -1)); }
+// The overlap-save tables of chunk length C, built and uploaded on first use
+// (the plan's device current).
+hipError_t ols_tables(fdas_plan* p, int C, const OlsTables** out);
+// Persistent-grid workgroups of the convolution at chunk length C.
+inline int ols_slots(const fdas_plan* p, int C) { return p->cus * ols_slots_per_cu(C); }
 
 // Make the plan's device current for the duration of a call.
 struct DeviceGuard {

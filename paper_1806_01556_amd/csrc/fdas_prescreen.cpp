@@ -337,7 +337,9 @@ fdas_status fdas_search_blocks(fdas_plan* p, const void* d_spectrum, int64_t n, 
   }
   // overlap-save chunks whose valid outputs touch a searched block (every
   // template) or only source blocks (the source rows)
-  const int V = p->geom.V;
+  const OlsTables& ot = p->ols[p->ols_idx];
+  const int slots = ols_slots(p, ot.geom.C);
+  const int V = ot.geom.V;
   std::vector<int> chunks, src_chunks;
   const int64_t nchunks = (n + V - 1) / V;
   for (int64_t c = 0; c < nchunks; ++c) {
@@ -378,12 +380,11 @@ fdas_status fdas_search_blocks(fdas_plan* p, const void* d_spectrum, int64_t n, 
     return hip_fail(e, "uploading the block lists");
   if (tiles.empty()) e = launch_fill_i32(d_counts, nh, 0, s);  // else the harmonic sum resets them
   if (e == hipSuccess && !chunks.empty())
-    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2, 0,
-                             p->rows, p->geom, p->conv_slots, p->d_lists, (int)chunks.size(), s);
+    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, ot, 0, p->rows, p->desc.z_max,
+                             slots, p->d_lists, (int)chunks.size(), s);
   if (e == hipSuccess && !src_chunks.empty())
-    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2, r_lo,
-                             r_hi - r_lo + 1, p->geom, p->conv_slots, p->d_lists + chunks.size(),
-                             (int)src_chunks.size(), s);
+    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, ot, r_lo, r_hi - r_lo + 1,
+                             p->desc.z_max, slots, p->d_lists + chunks.size(), (int)src_chunks.size(), s);
   if (e == hipSuccess && !tiles.empty()) {
     HsWork wk{p->d_lists + chunks.size() + src_chunks.size(), (int)tiles.size(), p->d_hitrows, p->d_hitrow_count,
               p->tuning.emit_workgroups};
@@ -427,7 +428,9 @@ fdas_status fdas_search_flagged(fdas_plan* p, const void* d_spectrum, int64_t n,
   }
   // lists sized for the whole spectrum: every chunk twice (searched, source
   // only), every tile, three counts
-  const int V = p->geom.V;
+  const OlsTables& ot = p->ols[p->ols_idx];
+  const int slots = ols_slots(p, ot.geom.C);
+  const int V = ot.geom.V;
   const int tcols = harmsum_tile_columns();
   const int cap_c = (int)((n + V - 1) / V);
   const int cap_t = (int)((n + tcols - 1) / tcols);
@@ -450,11 +453,11 @@ fdas_status fdas_search_flagged(fdas_plan* p, const void* d_spectrum, int64_t n,
   stretch_source_rows(p->desc.z_max, nh, &r_lo, &r_hi);
   e = ps_search_lists(d_logits, threshold, n, (int)nblk, nh, V, tcols, lists, cap_c, cap_t, s);
   if (e == hipSuccess)
-    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2, 0,
-                             p->rows, p->geom, p->conv_slots, lists, cap_c, s, counts3);
+    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, ot, 0, p->rows, p->desc.z_max,
+                             slots, lists, cap_c, s, counts3);
   if (e == hipSuccess)
-    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, p->d_H, p->d_tw1, p->d_tw2, r_lo,
-                             r_hi - r_lo + 1, p->geom, p->conv_slots, lists + cap_c + cap_t, cap_c, s, counts3 + 2);
+    e = launch_ols_conv_list(static_cast<const float2*>(d_spectrum), n, d_fop, ld, ot, r_lo, r_hi - r_lo + 1,
+                             p->desc.z_max, slots, lists + cap_c + cap_t, cap_c, s, counts3 + 2);
   if (e == hipSuccess) {
     // every tile slot gets a workgroup; slots past the selection hold -1 and exit
     HsWork wk{lists + cap_c, cap_t, p->d_hitrows, p->d_hitrow_count, p->tuning.emit_workgroups};

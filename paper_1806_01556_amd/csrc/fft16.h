@@ -117,5 +117,28 @@ __host__ __device__ __forceinline__ void fft16(float2 (&v)[16]) {
 
 __host__ __device__ constexpr int perm16(int p) { return (p >> 2) + 4 * (p & 3); }
 
+// 8-point DFT, exponent sign S, in place, natural order in and out: the even
+// and odd samples are two 4-point DFTs E, O and X[k] = E[k] + w8^(S k) O[k],
+// X[k + 4] = E[k] - w8^(S k) O[k], with w8 = R2 (1 + i), w8^2 = i, w8^3 = R2 (-1 + i).
+template <int S>
+__host__ __device__ __forceinline__ void dft8(float2& x0, float2& x1, float2& x2, float2& x3, float2& x4,
+                                              float2& x5, float2& x6, float2& x7) {
+  dft4<S>(x0, x2, x4, x6);  // E[0..3] in x0, x2, x4, x6
+  dft4<S>(x1, x3, x5, x7);  // O[0..3] in x1, x3, x5, x7
+  const float2 o1 = one_pi<S>(x3), o3 = mone_pi<S>(x7);  // / R2
+  const float2 w1 = make_float2(kR2 * o1.x, kR2 * o1.y);
+  const float2 w2 = make_float2(-S * x5.y, S * x5.x);
+  const float2 w3 = make_float2(kR2 * o3.x, kR2 * o3.y);
+  const float2 e0 = x0, e1 = x2, e2 = x4, e3 = x6, w0 = x1;
+  x0 = cadd(e0, w0);
+  x4 = csub(e0, w0);
+  x1 = cadd(e1, w1);
+  x5 = csub(e1, w1);
+  x2 = cadd(e2, w2);
+  x6 = csub(e2, w2);
+  x3 = cadd(e3, w3);
+  x7 = csub(e3, w3);
+}
+
 }  // namespace fft
 }  // namespace fdas

@@ -347,7 +347,7 @@ __device__ __forceinline__ void hs_phase1_thread(const float* __restrict__ fop, 
 template <int Z, int NH>
 __device__ __forceinline__ void hs_load_ta(const float* __restrict__ ta, float* __restrict__ s_ta) {
   constexpr int ROWS = 2 * Z + 1;
-  for (int e = threadIdx.x; e < ROWS * 8; e += HS_THREADS) {
+  for (int e = threadIdx.x; e < ROWS * 8; e += blockDim.x) {
     const int r = e / 8, m = e % 8;
     s_ta[e] = m < NH ? ta[m * ROWS + r] : 0.0f;
   }
@@ -367,22 +367,22 @@ __device__ __forceinline__ void hs_flush_entries(const int4* __restrict__ s_ent,
 // ld >= n and ld % 4 == 0; a source column j/k + 1 read for k >= 2 is at most
 // (n-1)/2 + 1 <= ld - 1.  Values read beyond column n - 1 only reach columns
 // >= n, which phase 2 never emits.
-template <int Z, int NH>
-__global__ __launch_bounds__(HS_THREADS) void k_harmsum_z(const float* __restrict__ fop, int64_t ld, int n,
+template <int Z, int NH, int TH = HS_THREADS>
+__global__ __launch_bounds__(TH) void k_harmsum_z(const float* __restrict__ fop, int64_t ld, int n,
                                                           const int* __restrict__ tile_of_block,
                                                           const float* __restrict__ ta, int4* __restrict__ hitrows,
                                                           int32_t* __restrict__ hitrow_count) {
   constexpr int ROWS = 2 * Z + 1;
   static_assert(ROWS <= 96, "hit mask holds 96 rows");
   __shared__ float s_ta[ROWS * 8];  // [row][k-1]
-  __shared__ int4 s_ent[HS_THREADS];
+  __shared__ int4 s_ent[TH];
   __shared__ int s_nent, s_base;
   hs_load_ta<Z, NH>(ta, s_ta);
   if (threadIdx.x == 0) s_nent = 0;
   __syncthreads();
   const int groups = (n + 3) / 4;
   const int tile = tile_of_block[blockIdx.x];  // -1: no tile for this block
-  const int g = tile * HS_THREADS + threadIdx.x;
+  const int g = tile * TH + threadIdx.x;
   if (tile >= 0 && g < groups) {
     const int j0 = 4 * g;
     unsigned mask[3];
@@ -399,15 +399,15 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_z(const float* __restric
 // Batch form: workgroup blk_begin + blockIdx.x belongs to the last trial whose
 // block0 is <= it; its tile comes from that trial's tile order.  Entries carry
 // the trial in bits 21..31 of the third mask word (rows 64..84 use bits 0..20).
-template <int Z, int NH>
-__global__ __launch_bounds__(HS_THREADS) void k_harmsum_z_batch(const HsTrial* __restrict__ trials, int ntrials,
+template <int Z, int NH, int TH>
+__global__ __launch_bounds__(TH) void k_harmsum_z_batch(const HsTrial* __restrict__ trials, int ntrials,
                                                                 int blk_begin, const float* __restrict__ ta,
                                                                 int4* __restrict__ hitrows,
                                                                 int32_t* __restrict__ hitrow_count) {
   constexpr int ROWS = 2 * Z + 1;
   static_assert(ROWS <= 85, "the trial tag uses bits 21..31 of the third mask word");
   __shared__ float s_ta[ROWS * 8];
-  __shared__ int4 s_ent[HS_THREADS];
+  __shared__ int4 s_ent[TH];
   __shared__ int s_nent, s_base;
   hs_load_ta<Z, NH>(ta, s_ta);
   if (threadIdx.x == 0) s_nent = 0;
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_z_batch(const HsTrial* _
   const int groups = (tr.n + 3) / 4;
   const int lb = b - tr.block0;
   const int tile = lb < tr.nblocks ? tr.tile_of_block[lb] : -1;
-  const int g = tile * HS_THREADS + threadIdx.x;
+  const int g = tile * TH + threadIdx.x;
   if (tile >= 0 && g < groups) {
     const int j0 = 4 * g;
     unsigned mask[3];
@@ -722,18 +722,49 @@ hipError_t launch_zero_counts_batch(const HsTrial* trials, int ntrials, int nh, 
   return hipGetLastError();
 }
 
+template <int TH>
+hipError_t launch_phase1_batch(const HsTrial* trials, int ntrials, int blk_begin, unsigned blocks, int n_harm,
+                               const float* ta, int4* hitrows, int32_t* hitrow_count, hipStream_t s) {
+  switch (n_harm) {
+#define FDAS_HSP_CASE(NH)                                                                                     \
+  case NH:                                                                                                    \
+    hipLaunchKernelGGL((k_harmsum_z_batch<42, NH, TH>), dim3(blocks), dim3(TH), 0, s, trials, ntrials,        \
+                       blk_begin, ta, hitrows, hitrow_count);                                                 \
+    break;
+    FDAS_HSP_CASE(1)
+    FDAS_HSP_CASE(2)
+    FDAS_HSP_CASE(3)
+    FDAS_HSP_CASE(4)
+    FDAS_HSP_CASE(5)
+    FDAS_HSP_CASE(6)
+    FDAS_HSP_CASE(7)
+    FDAS_HSP_CASE(8)
+#undef FDAS_HSP_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool harmsum_tile_built(int cols) { return cols == 256 || cols == 512 || cols == 1024; }
+
 hipError_t launch_harmsum_batch85(const HsTrial* trials, int ntrials, int blk_begin, int blk_end, int n_harm,
                                   const float* ta, int cap, int4* hitrows, int32_t* hitrow_count, int eblocks,
-                                  hipStream_t s) {
+                                  int tile_cols, hipStream_t s) {
   if (blk_end <= blk_begin) return hipSuccess;
   hipError_t e = launch_fill_i32(hitrow_count, 1, 0, s);
   if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)(blk_end - blk_begin);
+  switch (tile_cols) {
+    case 256: e = launch_phase1_batch<64>(trials, ntrials, blk_begin, blocks, n_harm, ta, hitrows, hitrow_count, s); break;
+    case 512: e = launch_phase1_batch<128>(trials, ntrials, blk_begin, blocks, n_harm, ta, hitrows, hitrow_count, s); break;
+    case 1024: e = launch_phase1_batch<256>(trials, ntrials, blk_begin, blocks, n_harm, ta, hitrows, hitrow_count, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
   switch (n_harm) {
 #define FDAS_HSB_CASE(NH)                                                                                     \
   case NH:                                                                                                    \
-    hipLaunchKernelGGL((k_harmsum_z_batch<42, NH>), dim3(blocks), dim3(HS_THREADS), 0, s, trials, ntrials,    \
-                       blk_begin, ta, hitrows, hitrow_count);                                                 \
     hipLaunchKernelGGL((k_harmsum_emit_batch<42, NH>), dim3(eblocks), dim3(HS_THREADS), 0, s, trials, hitrows, \
                        hitrow_count, ta, cap);                                                                \
     break;

@@ -73,9 +73,11 @@ class Trial(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [
         ("conv_templates_per_item", ctypes.c_int32),
-        ("conv_workgroups_per_cu", ctypes.c_int32),
+        ("conv_waves_per_simd", ctypes.c_int32),
         ("overlap_groups", ctypes.c_int32),
         ("emit_workgroups", ctypes.c_int32),
+        ("ols_chunk", ctypes.c_int32),
+        ("hsum_tile", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -1,5 +1,5 @@
-// Host check of the 16-point DFT building block of the overlap-save
-// convolution (fdas::fft::fft16, both exponent signs) against a DFT summed in
+// Host check of the 16- and 8-point DFT building blocks of the overlap-save
+// convolution (fdas::fft::fft16 and dft8, both exponent signs) against a DFT summed in
 // double precision, on random inputs.  Prints the worst absolute error and
 // exits non-zero above the bound.
 #include <cmath>
@@ -31,6 +31,31 @@ int main() {
           im += xr[n] * std::sin(a) + xi[n] * std::cos(a);
         }
         worst = std::fmax(worst, std::fmax(std::fabs(v[p].x - re), std::fabs(v[p].y - im)));
+      }
+    }
+  }
+  // 8-point DFT (natural order in and out)
+  for (int trial = 0; trial < 4000; ++trial) {
+    for (int S : {1, -1}) {
+      float2 v[8];
+      double xr[8], xi[8];
+      for (int i = 0; i < 8; ++i) {
+        v[i] = make_float2(nd(rng), nd(rng));
+        xr[i] = v[i].x;
+        xi[i] = v[i].y;
+      }
+      if (S > 0)
+        fdas::fft::dft8<1>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
+      else
+        fdas::fft::dft8<-1>(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]);
+      for (int k = 0; k < 8; ++k) {
+        double re = 0.0, im = 0.0;
+        for (int n = 0; n < 8; ++n) {
+          const double a = S * 2.0 * M_PI * n * k / 8.0;
+          re += xr[n] * std::cos(a) - xi[n] * std::sin(a);
+          im += xr[n] * std::sin(a) + xi[n] * std::cos(a);
+        }
+        worst = std::fmax(worst, std::fmax(std::fabs(v[k].x - re), std::fabs(v[k].y - im)));
       }
     }
   }

@@ -87,8 +87,10 @@ def plan42():
 
 
 @pytest.mark.parametrize("tuning", [{}, {"overlap_groups": 2}, {"overlap_groups": 3, "conv_templates_per_item": 9},
-                                    {"conv_workgroups_per_cu": 1, "conv_templates_per_item": 85,
-                                     "emit_workgroups": 256}])
+                                    {"conv_waves_per_simd": 1, "conv_templates_per_item": 85,
+                                     "emit_workgroups": 256},
+                                    {"hsum_tile": 256}, {"hsum_tile": 512, "overlap_groups": 2},
+                                    {"ols_chunk": 4096, "hsum_tile": 1024}])
 def test_batch_matches_single_calls_bit_for_bit(tuning):
     plan = plan42()
     fdas.set_tuning(plan, **tuning)
@@ -181,20 +183,48 @@ def test_batch_on_plans_without_the_graphed_path(kind):
         plan.destroy()
 
 
+@pytest.mark.parametrize("chunk", [2048, 8192])
+def test_batch_at_other_chunk_lengths_matches_single_calls(chunk):
+    """The batch at chunk length C equals the single calls of a plan built for
+    C bit for bit, for every tile width."""
+    plan = fdas.plan_create(n_max=1 << 17, ols_chunk=chunk)
+    try:
+        specs = _specs(LENGTHS, 700 + chunk)
+        for tile in (256, 1024):
+            fdas.set_tuning(plan, ols_chunk=chunk, hsum_tile=tile)
+            b = Batch(plan, specs)
+            got, counts = b.run()
+            for i, s in enumerate(specs):
+                n = s.shape[0]
+                fop1, c1, hc1 = _single(plan, s)
+                assert torch.equal(b.fop[i][:, :n], fop1[:, :n]), f"C={chunk} trial {i} (n={n}): FOP differs"
+                _same(got[i], c1)
+                assert np.array_equal(counts[i], hc1)
+    finally:
+        plan.destroy()
+
+
 def test_autotune_keeps_results():
     plan = fdas.plan_create(n_max=1 << 17)
+    other = None
     try:
         specs = _specs([40000, 100000, 70000, 9000], 61)
         b = Batch(plan, specs)
         t = fdas.autotune(plan, b.trials, repeats=2)
         print("autotune:", t, flush=True)
-        assert 0 <= t["conv_templates_per_item"] <= 85 and t["conv_workgroups_per_cu"] in (1, 2)
+        assert 0 <= t["conv_templates_per_item"] <= 85 and t["conv_waves_per_simd"] in (1, 2)
+        assert t["ols_chunk"] in (2048, 4096, 8192) and t["hsum_tile"] in (256, 512, 1024)
         got, _ = b.run()
+        # the chosen chunk length computes the plane of a plan built for it
+        ref = plan if t["ols_chunk"] == 4096 else fdas.plan_create(n_max=1 << 17, ols_chunk=t["ols_chunk"])
+        other = ref if ref is not plan else None
         for i, s in enumerate(specs):
-            _, c1, _ = _single(plan, s)
+            _, c1, _ = _single(ref, s)
             _same(got[i], c1)
     finally:
         plan.destroy()
+        if other is not None:
+            other.destroy()
 
 
 def test_batch_argument_errors():
@@ -213,6 +243,12 @@ def test_batch_argument_errors():
     t = fdas.Tuning()
     t.overlap_groups = 9
     assert L.fdas_set_tuning(plan.handle, t) == fdas.ERR_INVALID_ARG
+    t = fdas.Tuning()
+    t.ols_chunk = 1024
+    assert L.fdas_set_tuning(plan.handle, t) == fdas.ERR_UNSUPPORTED
+    t = fdas.Tuning()
+    t.hsum_tile = 2048
+    assert L.fdas_set_tuning(plan.handle, t) == fdas.ERR_UNSUPPORTED
 
 
 def test_many_trials_in_one_readback():

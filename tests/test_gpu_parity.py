@@ -37,11 +37,15 @@ def _dev():
 _plans = {}
 
 
-def plan_for(z_max=42, n_harm=8, n_max=1 << 22, cap=65536, top_k=0):
-    key = (z_max, n_harm, n_max, cap, top_k)
+def plan_for(z_max=42, n_harm=8, n_max=1 << 22, cap=65536, top_k=0, chunk=0):
+    key = (z_max, n_harm, n_max, cap, top_k, chunk)
     if key not in _plans:
-        _plans[key] = fdas.plan_create(z_max=z_max, n_harm=n_harm, n_max=n_max, cand_capacity=cap, top_k=top_k)
+        _plans[key] = fdas.plan_create(z_max=z_max, n_harm=n_harm, n_max=n_max, cand_capacity=cap, top_k=top_k,
+                                       ols_chunk=chunk)
     return _plans[key]
+
+
+CHUNKS = [2048, 4096, 8192]
 
 
 def gpu_fop(plan, spec, ld=None):
@@ -72,9 +76,10 @@ def assert_fop_close(got, ref):
 
 # --------------------------------------------------------------------------- conv
 
-@pytest.mark.parametrize("n", [1, 3, 64, 1000, 3703, 3704, 4096, 7407, 12345])
-def test_convolve_ragged_lengths(n):
-    plan = plan_for()
+@pytest.mark.parametrize("chunk", CHUNKS)
+@pytest.mark.parametrize("n", [1, 3, 64, 1000, 1655, 1656, 3703, 3704, 4096, 7407, 7799, 7800, 12345, 20000])
+def test_convolve_ragged_lengths(n, chunk):
+    plan = plan_for(chunk=chunk)
     spec, _ = synth.make_spectrum(n, 100 + n)
     got = gpu_fop(plan, spec).cpu().numpy()
     ref = ofop.fop(spec.astype(np.complex128))
@@ -82,18 +87,20 @@ def test_convolve_ragged_lengths(n):
     assert np.all(np.isnan(got[:, n:])), "columns >= n must not be written"
 
 
+@pytest.mark.parametrize("chunk", CHUNKS)
 @pytest.mark.parametrize("z_max", [0, 1, 5, 17, 64])
-def test_convolve_other_template_counts(z_max):
+def test_convolve_other_template_counts(z_max, chunk):
     n = 9000
-    plan = plan_for(z_max=z_max, n_max=1 << 16)
+    plan = plan_for(z_max=z_max, n_max=1 << 16, chunk=chunk)
     spec, _ = synth.make_spectrum(n, 7 + z_max, n_random=2, r_range=(500, 8000))
     got = gpu_fop(plan, spec).cpu().numpy()[:, :n]
     ref = ofop.fop(spec.astype(np.complex128), z_max=z_max)
     assert_fop_close(got, ref)
 
 
-def test_convolve_plain_workload_full_plane():
-    plan = plan_for()
+@pytest.mark.parametrize("chunk", CHUNKS)
+def test_convolve_plain_workload_full_plane(chunk):
+    plan = plan_for(chunk=chunk)
     spec, _ = synth.plain()
     n = spec.shape[0]
     got = gpu_fop(plan, spec).cpu().numpy()[:, :n]
@@ -106,19 +113,21 @@ def test_convolve_plain_workload_full_plane():
 
 
 @pytest.mark.timeout(900)
-def test_convolve_ska_size_full_plane():
-    # Full SKA length in the bench's launch configuration: every cell of the
-    # 85 x 2^22 plane against the FP64 oracle (eq. (2) in FP64), and a few
-    # chunk-boundary columns against the direct sum of eq. (1) as well.
-    plan = plan_for()
+@pytest.mark.parametrize("chunk", [4096, 2048, 8192])
+def test_convolve_ska_size_full_plane(chunk):
+    # Full SKA length in the bench's launch configuration (C = 4096) and at the
+    # other chunk lengths: every cell of the 85 x 2^22 plane against the FP64
+    # oracle (eq. (2) in FP64), and a few chunk-boundary columns against the
+    # direct sum of eq. (1) as well.
+    plan = plan_for(chunk=chunk)
     spec, _, plane64, _, _, _ = skaref.ska()
     n = spec.shape[0]
     got = gpu_fop(plan, spec).cpu().numpy()
     worst = skaref.assert_plane_close(got, plane64)
-    print(f"ska 2^22 FOP, all {85 * n} cells: worst |err|/bound = {worst:.3g}", flush=True)
+    print(f"ska 2^22 FOP (C = {chunk}), all {85 * n} cells: worst |err|/bound = {worst:.3g}", flush=True)
     assert np.all(np.isnan(got[:, n:])), "columns >= n must not be written"
-    V = 4096 - 393
-    cc = np.repeat(np.array([0, V - 1, V, 1000 * V - 1, 1000 * V, n - 1]), 85)
+    V = chunk - 393
+    cc = np.repeat(np.array([0, V - 1, V, 400 * V - 1, 400 * V, n - 1]), 85)
     rr = np.tile(np.arange(85), 6)
     assert_fop_close(got[rr, cc], ofop.fop_points(spec.astype(np.complex128), rr, cc))
 
