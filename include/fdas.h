@@ -171,7 +171,8 @@ fdas_status fdas_harmonic_sum_noalloc(fdas_plan* plan, const float* d_fop, int64
 /* Copy the candidate lists back (after the work queued on stream), order them
  * by (harm, z, r) and write at most h_capacity records to h_out.  With
  * top_k > 0 each plane keeps its top_k highest powers (ties: lower z, then
- * lower r, first) before ordering.  *h_n receives the number written.
+ * lower r, first; N_cand of Table 1), selected on the device, still in
+ * (harm, z, r) order.  *h_n receives the number written.
  * h_counts (optional, int32[n_harm]; NULL to skip) receives the device counts,
  * the true per-plane totals that tell a caller how much an overflowed list
  * lost; they are read in the same wait as the records.
@@ -249,8 +250,8 @@ fdas_status fdas_set_tuning(fdas_plan* plan, const fdas_tuning* tuning);
  * owned by the plan, written by the device itself, so the call waits once
  * (no intermediate wait for the counts).  *h_view points at *h_n records in
  * (harm, z, r) order, valid until the plan's next fdas_candidates_mapped or
- * fdas_plan_destroy.  h_counts as in fdas_candidates.  With top_k > 0 the
- * selection runs on the host as in fdas_candidates.  Synchronises. */
+ * fdas_plan_destroy.  h_counts as in fdas_candidates.  With top_k > 0 each
+ * plane keeps its top_k highest powers as in fdas_candidates.  Synchronises. */
 fdas_status fdas_candidates_mapped(fdas_plan* plan, const fdas_cand* d_cands, const int32_t* d_counts,
                                    const fdas_cand** h_view, int64_t* h_n, int32_t* h_counts, void* stream);
 

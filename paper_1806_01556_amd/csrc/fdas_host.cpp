@@ -482,29 +482,25 @@ fdas_status fdas_candidates(fdas_plan* p, const fdas_cand* d_cands, const int32_
     if (counts[k] > cap) overflow = true;
     off[k + 1] = off[k] + std::min(counts[k], cap);
   }
-  const int total = off[nh];
-  int64_t nw = 0;
-  if (p->desc.top_k <= 0) {
-    nw = std::min<int64_t>(total, h_capacity);
-    if (nw > 0) e = hipMemcpyAsync(h_out, sorted, (size_t)nw * sizeof(fdas_cand), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "reading candidates");
-  } else {
-    // paper mode: each plane keeps its top_k powers (ties: lower z, then lower r)
-    std::vector<fdas_cand> all(total);
-    if (total > 0) e = hipMemcpyAsync(all.data(), sorted, (size_t)total * sizeof(fdas_cand), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "reading candidates");
-    std::vector<fdas_cand> keep;
-    keep_top_k(all.data(), off, nh, p->desc.top_k, keep);
-    nw = std::min<int64_t>((int64_t)keep.size(), h_capacity);
-    if (nw > 0) std::memcpy(h_out, keep.data(), (size_t)nw * sizeof(fdas_cand));
-    if (nw < (int64_t)keep.size()) overflow = true;
+  int total = off[nh];
+  const fdas_cand* src = sorted;
+  if (p->desc.top_k > 0) {
+    // paper mode (Table 1's N_cand): each plane keeps its top_k powers (ties:
+    // lower z, then lower r), selected on the device into the other buffer
+    fdas_cand* kept = sorted == p->d_sort_a ? p->d_sort_b : p->d_sort_a;
+    e = fdas::launch_topk(sorted, cap, nh, d_counts, p->desc.top_k, kept, s);
+    if (e != hipSuccess) return hip_fail(e, "selecting the top candidates");
+    src = kept;
+    total = 0;
+    for (int k = 0; k < nh; ++k) total += std::min(off[k + 1] - off[k], p->desc.top_k);
   }
+  const int64_t nw = std::min<int64_t>(total, h_capacity);
+  if (nw > 0) e = hipMemcpyAsync(h_out, src, (size_t)nw * sizeof(fdas_cand), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "reading candidates");
   *h_n = nw;
   if (overflow) return fail(FDAS_ERR_CAPACITY, "a device candidate list overflowed (counts are exact)");
-  if (p->desc.top_k <= 0 && nw < total)
-    return fail(FDAS_ERR_CAPACITY, "h_capacity %lld < %d candidates", (long long)h_capacity, total);
+  if (nw < total) return fail(FDAS_ERR_CAPACITY, "h_capacity %lld < %d candidates", (long long)h_capacity, total);
   return ok();
 }
 
@@ -517,21 +513,6 @@ fdas_status fdas_candidates_mapped(fdas_plan* p, const fdas_cand* d_cands, const
   if (!h_view || !h_n) return fail(FDAS_ERR_INVALID_ARG, "h_view or h_n is NULL");
   *h_view = nullptr;
   *h_n = 0;
-  if (p->desc.top_k > 0) {
-    // paper mode selects on the host; serve it through the copying call
-    const int64_t cap = (int64_t)p->desc.n_harm * p->desc.top_k;
-    if (!p->h_result) {
-      hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p->h_result),
-                                   (size_t)p->desc.n_harm * p->desc.cand_capacity * sizeof(fdas_cand), 0);
-      if (e != hipSuccess) {
-        p->h_result = nullptr;
-        return hip_fail(e, "allocating the page-locked result buffer");
-      }
-    }
-    fdas_status st = fdas_candidates(p, d_cands, d_counts, p->h_result, cap, h_n, h_counts, stream);
-    *h_view = p->h_result;
-    return st;
-  }
   DeviceGuard dg(p->device);
   if (dg.err != hipSuccess) return hip_fail(dg.err, "hipSetDevice");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -554,11 +535,18 @@ fdas_status fdas_candidates_mapped(fdas_plan* p, const fdas_cand* d_cands, const
       (e = hipHostGetDevicePointer(&d_rc, p->h_result_counts, 0)) != hipSuccess)
     return hip_fail(e, "mapping the result buffer");
   fdas_cand* sorted = nullptr;
+  const int keep = p->desc.top_k > 0 ? std::min(p->desc.top_k, cap) : 0;
   e = fdas::launch_sort_candidates(d_cands, cap, nh, d_counts, p->rows, p->desc.z_max, p->bits_r, p->d_sort_a,
                                    p->d_sort_b, p->d_sort_hist, p->d_sort_totals, &sorted, s);
+  if (e == hipSuccess && keep > 0) {
+    // paper mode: the top-k selection on the device, into the other buffer
+    fdas_cand* kept = sorted == p->d_sort_a ? p->d_sort_b : p->d_sort_a;
+    e = fdas::launch_topk(sorted, cap, nh, d_counts, keep, kept, s);
+    sorted = kept;
+  }
   if (e == hipSuccess)
     e = fdas::launch_copy_out(sorted, cap, nh, d_counts, nh * cap, static_cast<fdas_cand*>(d_res),
-                              static_cast<int32_t*>(d_rc), s);
+                              static_cast<int32_t*>(d_rc), s, keep);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) return hip_fail(e, "ordering and reading candidates");
   const int32_t* counts = p->h_result_counts;
@@ -568,7 +556,7 @@ fdas_status fdas_candidates_mapped(fdas_plan* p, const fdas_cand* d_cands, const
   for (int k = 0; k < nh; ++k) {
     if (counts[k] < 0) return fail(FDAS_ERR_DEVICE, "negative candidate count");
     if (counts[k] > cap) overflow = true;
-    total += std::min(counts[k], cap);
+    total += keep > 0 ? std::min(std::min(counts[k], cap), keep) : std::min(counts[k], cap);
   }
   *h_view = p->h_result;
   *h_n = total;

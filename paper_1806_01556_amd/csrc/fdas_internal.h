@@ -175,9 +175,17 @@ int sort_tile_count(int m);
 int sort_passes(int rows, int bits_r);
 
 // Ordered records [0, min(total, out_cap)) and the nh counts copied into
-// device-visible page-locked host memory by a kernel.
+// device-visible page-locked host memory by a kernel; with keep > 0 every
+// plane holds at most keep records (the layout launch_topk writes).
 hipError_t launch_copy_out(const fdas_cand* sorted, int cap, int nh, const int32_t* counts, int out_cap,
-                           fdas_cand* out, int32_t* counts_out, hipStream_t s);
+                           fdas_cand* out, int32_t* counts_out, hipStream_t s, int keep = 0);
+
+// Table 1's N_cand per plane on the device: from the ordered array (planes
+// packed, min(count, cap) records each) keep each plane's top_k highest
+// powers (ties: lower z, then lower r), in (z, r) order, packed into out
+// (plane k after sum_{k' < k} min(top_k, its records)).
+hipError_t launch_topk(const fdas_cand* sorted, int cap, int nh, const int32_t* counts, int top_k, fdas_cand* out,
+                       hipStream_t s);
 
 // out[t * nh + k] = ptrs[t][k] for t < count, k < nh
 hipError_t launch_gather_counts(int32_t* const* ptrs, int count, int nh, int32_t* out, hipStream_t s);

@@ -49,12 +49,14 @@ __device__ __forceinline__ unsigned long long cand_key(const int4 c, const CandK
 }
 
 // plane offsets of the packed array from the device counts (each plane keeps
-// at most cap records); returns the total
-__device__ __forceinline__ int pack_offsets(const int32_t* __restrict__ counts, int nh, int cap, int (&off)[9]) {
+// at most cap records, and at most keep of them when keep > 0); returns the total
+__device__ __forceinline__ int pack_offsets(const int32_t* __restrict__ counts, int nh, int cap, int (&off)[9],
+                                            int keep = 0) {
   off[0] = 0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    const int c = k < nh ? min(max(counts[k], 0), cap) : 0;
+    int c = k < nh ? min(max(counts[k], 0), cap) : 0;
+    if (keep > 0) c = min(c, keep);
     off[k + 1] = off[k] + c;
   }
   return off[8];
@@ -243,14 +245,96 @@ __global__ __launch_bounds__(ST) void k_sort_pack_batch(const RbTrial* __restric
   out[i] = rec;
 }
 
+// Top-k selection of Table 1's N_cand per plane, on the ordered array: block
+// k keeps the top_k highest powers of plane k (ties: lower z, then lower r --
+// the earlier record of the (z, r)-ordered plane) and writes them, still in
+// (z, r) order, after the kept records of the planes before it.  The k-th
+// largest of the distinct keys (power bits << 32 | ~position) is found by an
+// 8-bit radix select from the top digit; the records with a key at least as
+// large are compacted in order by a workgroup scan.
+constexpr int TK = 1024;  // threads of the selection
+
+__device__ __forceinline__ unsigned long long topk_key(const int4* __restrict__ plane, int p) {
+  // powers of candidates are above a positive threshold: their bits order them
+  return ((unsigned long long)(unsigned)plane[p].w << 32) | (unsigned long long)(~(unsigned)p);
+}
+
+__global__ __launch_bounds__(TK) void k_topk(const int4* __restrict__ sorted, int cap, int nh,
+                                             const int32_t* __restrict__ counts, int top_k,
+                                             int4* __restrict__ out) {
+  __shared__ int s_hist[256];
+  __shared__ int s_scan[TK];
+  __shared__ unsigned long long s_prefix;
+  __shared__ int s_need;
+  const int k = blockIdx.x, t = threadIdx.x;
+  if (k >= nh) return;
+  int off[9], okeep[9];
+  pack_offsets(counts, nh, cap, off);
+  pack_offsets(counts, nh, cap, okeep, top_k);
+  const int m = off[k + 1] - off[k];
+  const int4* plane = sorted + off[k];
+  int4* dst = out + okeep[k];
+  if (m <= top_k) {
+    for (int i = t; i < m; i += TK) dst[i] = plane[i];
+    return;
+  }
+  // radix select of the top_k-th largest key
+  if (t == 0) {
+    s_prefix = 0ull;
+    s_need = top_k;
+  }
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int d = t; d < 256; d += TK) s_hist[d] = 0;
+    __syncthreads();
+    const unsigned long long prefix = s_prefix;
+    const unsigned long long hmask = shift == 56 ? 0ull : (~0ull << (shift + 8));
+    for (int i = t; i < m; i += TK) {
+      const unsigned long long key = topk_key(plane, i);
+      if ((key & hmask) == prefix) atomicAdd(&s_hist[(int)((key >> shift) & 255ull)], 1);
+    }
+    __syncthreads();
+    if (t == 0) {
+      // the digit D at which the count of keys with a larger digit stays
+      // below the need and the count with digit >= D reaches it
+      int need = s_need, above = 0, D = 255;
+      for (; D > 0; --D) {
+        if (above + s_hist[D] >= need) break;
+        above += s_hist[D];
+      }
+      s_need = need - above;
+      s_prefix = prefix | ((unsigned long long)D << shift);
+    }
+    __syncthreads();
+  }
+  const unsigned long long kth = s_prefix;  // keys are distinct: exactly top_k are >= kth
+  // stable compaction of the keys >= kth
+  int base = 0;
+  for (int i0 = 0; i0 < m; i0 += TK) {
+    const int i = i0 + t;
+    const int f = (i < m && topk_key(plane, i) >= kth) ? 1 : 0;
+    s_scan[t] = f;
+    __syncthreads();
+    for (int o = 1; o < TK; o <<= 1) {
+      const int u = t >= o ? s_scan[t - o] : 0;
+      __syncthreads();
+      s_scan[t] += u;
+      __syncthreads();
+    }
+    if (f) dst[base + s_scan[t] - 1] = plane[i];
+    base += s_scan[TK - 1];
+    __syncthreads();
+  }
+}
+
 // The ordered records and the counts written straight into page-locked host
 // memory (device-visible pointers), so the host waits once: records
-// [0, min(total, out_cap)) of `sorted`, counts[0 .. nh).
+// [0, min(total, out_cap)) of `sorted` (each plane limited to keep records
+// when keep > 0: `sorted` is then the top-k output), counts[0 .. nh).
 __global__ __launch_bounds__(ST) void k_copy_out(const int4* __restrict__ sorted, int cap, int nh,
-                                                 const int32_t* __restrict__ counts, int out_cap,
+                                                 const int32_t* __restrict__ counts, int out_cap, int keep,
                                                  int4* __restrict__ out, int32_t* __restrict__ counts_out) {
   int off[9];
-  const int m = min(pack_offsets(counts, nh, cap, off), out_cap);
+  const int m = min(pack_offsets(counts, nh, cap, off, keep), out_cap);
   if (blockIdx.x == 0 && (int)threadIdx.x < nh) counts_out[threadIdx.x] = counts[threadIdx.x];
   for (int i = blockIdx.x * ST + threadIdx.x; i < m; i += gridDim.x * ST) out[i] = sorted[i];
 }
@@ -258,10 +342,18 @@ __global__ __launch_bounds__(ST) void k_copy_out(const int4* __restrict__ sorted
 }  // namespace
 
 hipError_t launch_copy_out(const fdas_cand* sorted, int cap, int nh, const int32_t* counts, int out_cap,
-                           fdas_cand* out, int32_t* counts_out, hipStream_t s) {
+                           fdas_cand* out, int32_t* counts_out, hipStream_t s, int keep) {
   const int blocks = std::max(1, std::min(1024, (nh * cap + ST - 1) / ST));
   hipLaunchKernelGGL(k_copy_out, dim3(blocks), dim3(ST), 0, s, reinterpret_cast<const int4*>(sorted), cap, nh,
-                     counts, out_cap, reinterpret_cast<int4*>(out), counts_out);
+                     counts, out_cap, keep, reinterpret_cast<int4*>(out), counts_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_topk(const fdas_cand* sorted, int cap, int nh, const int32_t* counts, int top_k, fdas_cand* out,
+                       hipStream_t s) {
+  if (top_k <= 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_topk, dim3(nh), dim3(TK), 0, s, reinterpret_cast<const int4*>(sorted), cap, nh, counts, top_k,
+                     reinterpret_cast<int4*>(out));
   return hipGetLastError();
 }
 

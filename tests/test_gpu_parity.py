@@ -282,6 +282,27 @@ def test_mapped_and_copying_readbacks_agree(top_k):
         _assert_same_cands(a, b)
 
 
+@pytest.mark.parametrize("mapped", [False, True])
+def test_top_k_ties_and_long_lists(mapped):
+    # Table 1's N_cand on the device: a constant plane makes every harmonic
+    # sum of a plane equal, so the selection is decided by the tie rule alone
+    # (lower z, then lower r); a second plane mixes long lists and ties
+    plan = plan_for(top_k=200, cap=1 << 18)
+    n = 3001
+    rng = np.random.default_rng(9)
+    for plane in (np.full((85, n), 20.0, dtype=np.float32),
+                  np.round(rng.exponential(size=(85, n)) * 4.0).astype(np.float32)):
+        ta = oh.threshold_array(8, 42, 1e-6).astype(np.float32) * 0.5
+        cands, counts = fdas.alloc_cands(plan, _dev())
+        fdas.harmonic_sum(plan, _upload_plane(plane), n, cands, counts,
+                          ta=torch.from_numpy(ta).to(_dev()))
+        cap = None if mapped else 8 * 200
+        got, hc = fdas.candidates(plan, cands, counts, capacity=cap)
+        ref = oh.candidates(plane, 8, ta=ta, top_k=200)
+        assert np.array_equal(hc, oh.plane_counts(oh.candidates(plane, 8, ta=ta)))
+        _assert_same_cands(got, ref)
+
+
 def test_top_k_paper_mode():
     plan = plan_for(top_k=200)
     rng = np.random.default_rng(8)
