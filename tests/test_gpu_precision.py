@@ -15,8 +15,13 @@ taps, S = sum_d |X[j+d]| |h[d]|):
   replace the FP32 path).
 The per-template worst relative power error on sampled cells of SKA-sized
 spectra is printed for FP16 split, BF16 split, FP32 direct and FP32
-overlap-save.
+overlap-save; with FDAS_PRECISION_FULL=1 the same report covers every cell of
+the 16 spectra of 2^22 bins of the precision workload (seeds 4000 + s; about
+ten minutes of FP64 oracle time on 16 threads, so it is not part of the
+default run).
 """
+
+import os
 
 import numpy as np
 import pytest
@@ -25,6 +30,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 
+import skaref  # noqa: E402
 from oracle import fop as ofop  # noqa: E402
 from oracle import harmonic as oh  # noqa: E402
 from paper_1806_01556_amd import fdas, synth  # noqa: E402
@@ -144,6 +150,44 @@ def test_per_template_error_report_ska_size():
             e = rel_err(got, ref).reshape(85, cols.size).max(axis=1)
             worst[m] = np.maximum(worst[m], e)
     print("worst relative power error per template (z = -42..42), sampled cells of 4 x 2^22 spectra:")
+    for m in methods:
+        print(f"  {m:5s} max {worst[m].max():.3g}  median {np.median(worst[m]):.3g}  per z: "
+              + " ".join(f"{v:.2g}" for v in worst[m]), flush=True)
+    assert worst["fp16"].max() <= BOUND["fp16"]
+    assert worst["bf16"].max() <= BOUND["bf16"]
+    assert worst["fp32"].max() <= 1e-4 and worst["ols"].max() <= 1e-4
+
+
+@pytest.mark.timeout(3000)
+@pytest.mark.skipif(os.environ.get("FDAS_PRECISION_FULL") != "1",
+                    reason="16 full 2^22-bin oracle planes (~10 min of CPU); set FDAS_PRECISION_FULL=1")
+def test_per_template_error_report_full_precision_workload():
+    """The precision workload at its stated size: 16 spectra of 2^22 bins
+    (seeds 4000 + s, 16 pulsars each), every one of the 85 x 2^22 cells of
+    each, worst |P - P_ref| / max(P_ref, 1) per template against the FP64
+    oracle plane, for the split FP16 / BF16 and FP32 direct contractions and
+    the FP32 overlap-save path."""
+    methods = ["fp16", "bf16", "fp32", "ols"]
+    worst = {m: np.zeros(85) for m in methods}
+    cells = 0
+    for sidx in range(16):
+        spec, _ = synth.make_spectrum(1 << 22, 4000 + sidx, n_random=16, r_range=(1e4, 2e6))
+        n = spec.shape[0]
+        print(f"precision workload: spectrum {sidx + 1}/16, FP64 oracle plane", flush=True)
+        ref = ofop.fop(spec.astype(np.complex128), workers=skaref.cpu_workers())
+        for m in methods:
+            got = gpu_fop(plan_for(m), spec).cpu().numpy()
+            for r0 in range(0, 85, 5):
+                g = got[r0:r0 + 5, :n].astype(np.float64)
+                f = ref[r0:r0 + 5]
+                worst[m][r0:r0 + 5] = np.maximum(worst[m][r0:r0 + 5],
+                                                 np.max(np.abs(g - f) / np.maximum(f, 1.0), axis=1))
+            del got
+        cells += 85 * n
+        del ref
+        print(f"  worst so far: " + ", ".join(f"{m} {worst[m].max():.3g}" for m in methods), flush=True)
+    print(f"worst relative power error per template (z = -42..42), every cell of 16 x 2^22 spectra "
+          f"({cells} cells per method):")
     for m in methods:
         print(f"  {m:5s} max {worst[m].max():.3g}  median {np.median(worst[m]):.3g}  per z: "
               + " ".join(f"{v:.2g}" for v in worst[m]), flush=True)
