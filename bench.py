@@ -138,6 +138,49 @@ def cpu_baseline(spec, n_full, runs=3):
     }
 
 
+def bench_index_maps(args, torch, fdas, synth, dev):
+    """Harmonic sum of one 2^22-bin plane (85 templates, 8 harmonics) under each
+    index map: the stretch map of Algorithm 1 and the two alternatives built
+    behind the plan option hsum_index.  One FOP (the overlap-save convolution
+    of the headline spectrum) feeds all three; each call is timed with HIP
+    events on the current stream, candidates included (counts reset, list
+    appended), readback excluded."""
+    n = 1 << 22
+    spec, _ = synth.ska(n=n, seed=2)
+    x = torch.from_numpy(spec).to(dev)
+    maps = [("stretch", fdas.HSUM_STRETCH), ("fundamental", fdas.HSUM_FUNDAMENTAL),
+            ("highest", fdas.HSUM_HIGHEST)]
+    plans = {name: fdas.plan_create(n_max=n, hsum_index=idx) for name, idx in maps}
+    fop = fdas.alloc_fop(plans["stretch"], n, dev)
+    fdas.convolve(plans["stretch"], x, fop, n=n)
+    torch.cuda.synchronize()
+    plane_bytes = 85 * n * 4
+    out = {"metric": "harmonic_sum_ms_per_plane", "unit": "ms", "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": "ska_single_spectrum_2^22 FOP, 85 templates, 8 harmonics, p_fa 1e-6"},
+           "maps": {}}
+    steps = max(1, args.steps)
+    for name, _ in maps:
+        plan = plans[name]
+        cands, counts = fdas.alloc_cands(plan, dev)
+        for _ in range(max(1, args.warmup)):
+            fdas.harmonic_sum(plan, fop, n, cands, counts)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fdas.harmonic_sum(plan, fop, n, cands, counts)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        got, hc = fdas.candidates(plan, cands, counts, allow_overflow=True)
+        out["maps"][name] = {"ms": round(ms, 4), "plane_reads_GB_per_s": round(plane_bytes / (ms * 1e-3) / 1e9, 1),
+                             "candidates": int(got.size), "per_plane": [int(c) for c in hc]}
+        print(f"index map {name}: {ms:.4f} ms per plane, {got.size} candidates", flush=True)
+    for p in plans.values():
+        p.destroy()
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args, torch, fdas, synth, dev):
     """Batched dispersion trials: `trials` spectra of lengths drawn from
     {2^20, 2^21, 3*2^20, 2^22} (seeds 3000 + b, 0-4 pulsars each) per step,
@@ -512,10 +555,11 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="label the FOP-buffer copies made after timing (4 plain copies of known size, "
                          "also timed as the achievable HBM bandwidth) so HBM counters can be scaled to bytes")
-    ap.add_argument("--workload", choices=("ska", "batch", "prescreen"), default="ska",
+    ap.add_argument("--workload", choices=("ska", "batch", "prescreen", "index-maps"), default="ska",
                     help="ska: one 2^22-bin spectrum per step (the headline); batch: 64 dispersion trials of "
                          "uneven length per step through the batch calls; prescreen: train the learned block "
-                         "pre-screen on oracle-labelled spectra, then search 2^22-bin spectra on flagged blocks")
+                         "pre-screen on oracle-labelled spectra, then search 2^22-bin spectra on flagged blocks; "
+                         "index-maps: the harmonic sum of one 2^22-bin plane under each index map")
     ap.add_argument("--epochs", type=int, default=8, help="prescreen workload: training epochs")
     ap.add_argument("--train-spectra", type=int, default=10000,
                     help="prescreen workload: labelled spectra to train on (the rest pick the threshold)")
@@ -541,6 +585,8 @@ def main():
         return bench_batch(args, torch, fdas, synth, dev)
     if args.workload == "prescreen":
         return bench_prescreen(args, torch, fdas, synth, dev)
+    if args.workload == "index-maps":
+        return bench_index_maps(args, torch, fdas, synth, dev)
 
     n = 1 << 22
     spec, pulsars = synth.ska(n=n, seed=2)

@@ -104,86 +104,223 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum(const float* __restrict_
 // Alternative index maps (plan option hsum_index), any row count.  A pulsar
 // whose fundamental sits at (z, r) has its m-th harmonic at (m z, m r).
 //
-// Fundamental-anchored: HP_k(i, j) = HP_{k-1}(i, j) + FOP(k i, k j), a term
-// being 0 where (k i, k j) is outside the plane.  Cumulative in k.
-template <int NH>
-__global__ __launch_bounds__(HS_THREADS) void k_harmsum_fund(const float* __restrict__ fop, int64_t ld, int n,
-                                                             int z_max, const float* __restrict__ ta,
-                                                             fdas_cand* __restrict__ cands, int cap,
-                                                             int32_t* __restrict__ counts) {
-  const int64_t g = (int64_t)blockIdx.x * HS_THREADS + threadIdx.x;
-  const int64_t j0 = g * 4;
-  if (j0 >= n) return;
-  const int rows = 2 * z_max + 1;
-  for (int r = 0; r < rows; ++r) {
-    const int i = r - z_max;
-    const float* row = fop + (size_t)r * ld;
-    float hp[4];
+// Both kernels take a column tile of XT = 4 * HS_THREADS columns per
+// workgroup (tile from tile_of_block when given, else blockIdx.x) and give
+// thread t the columns tile * XT + t + HS_THREADS * a, a = 0..3, so that a
+// wave's load of one source row covers 64 consecutive output columns: 64
+// consecutive source columns for the fundamental, 64 at stride m for FOP(k i,
+// k j), 64 nearly consecutive ones (stretch factor <= 1) for rho(m j, k).
+// Candidates are appended with one atomic per wave and plane (hits are rare;
+// a dense plane still costs one reservation per wave).
+
+constexpr int XT = 4 * HS_THREADS;
+
+// Lane offsets inside the wave from ballots of each lane's 3-bit hit count;
+// the lowest active lane reserves the wave's slots in list m.  Every lane of
+// the wave calls this with the same m (the caller is wave-uniform).
+__device__ __forceinline__ void wave_append(int m, int i, const int (&col)[4], const float (&v)[4], unsigned bits,
+                                            fdas_cand* __restrict__ cands, int cap, int32_t* __restrict__ counts) {
+  const int c = __popc(bits);
+  const unsigned long long b0 = __ballot(c & 1), b1 = __ballot(c & 2), b2 = __ballot(c & 4);
+  const int total = __popcll(b0) + 2 * __popcll(b1) + 4 * __popcll(b2);
+  if (total == 0) return;  // uniform
+  auto below = [](unsigned long long b) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+  };
+  const int mine = below(b0) + 2 * below(b1) + 4 * below(b2);
+  const unsigned long long act = __ballot(1);
+  const int lead = (int)__builtin_ctzll(act);
+  int base = 0;
+  if ((int)(threadIdx.x & 63) == lead) base = atomicAdd(&counts[m - 1], total);
+  int slot = __shfl(base, lead) + mine;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) hp[a] = (j0 + a < n) ? row[j0 + a] : 0.0f;
-    {
-      const float t = ta[r];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        if (hp[a] > t && j0 + a < n) emit(1, i, (int)(j0 + a), hp[a], cands, cap, counts);
-    }
-#pragma unroll
-    for (int m = 2; m <= NH; ++m) {
-      const int si = m * i;
-      const bool rin = si >= -z_max && si <= z_max;
-      const float* src = fop + (size_t)(rin ? si + z_max : 0) * ld;
-      const float t = ta[(m - 1) * rows + r];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int64_t sj = (int64_t)m * (j0 + a);
-        const float v = (rin && sj < n) ? src[sj] : 0.0f;
-        hp[a] = hp[a] + v;
-        if (hp[a] > t && j0 + a < n) emit(m, i, (int)(j0 + a), hp[a], cands, cap, counts);
-      }
+  for (int a = 0; a < 4; ++a) {
+    if ((bits >> a) & 1u) {
+      if ((unsigned)slot < (unsigned)cap)
+        *reinterpret_cast<int4*>(cands + (size_t)(m - 1) * cap + slot) = make_int4(m, i, col[a], __float_as_int(v[a]));
+      ++slot;
     }
   }
 }
 
-// a / k rounded to the nearest integer, halves away from zero
-__device__ __forceinline__ int64_t round_div(int64_t a, int k) {
-  return a >= 0 ? (2 * a + k) / (2 * k) : -((-2 * a + k) / (2 * k));
+// Tile of this workgroup (-1: none) and the thread's four columns.
+__device__ __forceinline__ int xt_tile(const int* __restrict__ tile_of_block, int n) {
+  const int tile = tile_of_block ? tile_of_block[blockIdx.x] : (int)blockIdx.x;
+  return (tile >= 0 && (int64_t)tile * XT < n) ? tile : -1;
+}
+
+// Fundamental-anchored: HP_k(i, j) = HP_{k-1}(i, j) + FOP(k i, k j), a term
+// being 0 where (k i, k j) is outside the plane.  Cumulative in k.  A row's
+// loads (the fundamental and every harmonic's source row k i) are issued
+// together before its sums.
+template <int NH>
+__global__ __launch_bounds__(HS_THREADS) void k_harmsum_fund(const float* __restrict__ fop, int64_t ld, int n,
+                                                             int z_max, const int* __restrict__ tile_of_block,
+                                                             const float* __restrict__ ta,
+                                                             fdas_cand* __restrict__ cands, int cap,
+                                                             int32_t* __restrict__ counts) {
+  const int tile = xt_tile(tile_of_block, n);
+  if (tile < 0) return;  // uniform
+  const int rows = 2 * z_max + 1;
+  int col[4];
+  bool in[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    col[a] = tile * XT + (int)threadIdx.x + HS_THREADS * a;
+    in[a] = col[a] < n;
+  }
+  for (int r = 0; r < rows; ++r) {
+    const int i = r - z_max;
+    float v[NH + 1][4];
+    {
+      const float* row = fop + (size_t)r * ld;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) v[1][a] = in[a] ? row[col[a]] : 0.0f;
+    }
+#pragma unroll
+    for (int m = 2; m <= NH; ++m) {
+      const int si = m * i;
+      const bool rin = si >= -z_max && si <= z_max;  // uniform
+      const float* src = fop + (size_t)(rin ? si + z_max : 0) * ld;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int sj = m * col[a];  // < 2^31: the plan keeps NH * n_max below it
+        v[m][a] = (rin && sj < n) ? src[sj] : 0.0f;
+      }
+    }
+    float hp[4];
+#pragma unroll
+    for (int m = 1; m <= NH; ++m) {
+      const float t = ta[(m - 1) * rows + r];
+      unsigned bits = 0u;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        hp[a] = m == 1 ? v[1][a] : hp[a] + v[m][a];
+        bits |= (in[a] && hp[a] > t) ? 1u << a : 0u;
+      }
+      wave_append(m, i, col, hp, bits, cands, cap, counts);
+    }
+  }
 }
 
 // Highest-harmonic-anchored: HP_k(i, j) = sum_{m=1..k} FOP(rho(m i, k), rho(m j, k)),
 // summed in m order, rho = rounding to the nearest integer with halves away
 // from zero.  Every index is inside the plane; the planes are not cumulative.
+//
+// rho(m x, k) depends on m/k only, so the terms of all k <= NH read one value
+// per reduced fraction p/q (q <= NH): 22 fractions for NH = 8.  Each
+// fraction's four values stay in registers while its source row rho(p i, q)
+// is unchanged (it changes on about p/q of the rows).
+
+__host__ __device__ constexpr int gcd_c(int a, int b) { return b == 0 ? a : gcd_c(b, a % b); }
+
+// reduced fractions p/q, 1 <= p <= q <= nh, ordered by q, then p
+__host__ __device__ constexpr int frac_count(int nh) {
+  int c = 0;
+  for (int q = 1; q <= nh; ++q)
+    for (int p = 1; p <= q; ++p) c += gcd_c(p, q) == 1 ? 1 : 0;
+  return c;
+}
+__host__ __device__ constexpr int frac_index(int m, int k) {
+  const int g = gcd_c(m, k), p = m / g, q = k / g;
+  int idx = frac_count(q - 1);
+  for (int pp = 1; pp < p; ++pp) idx += gcd_c(pp, q) == 1 ? 1 : 0;
+  return idx;
+}
+__host__ __device__ constexpr int frac_num(int idx) {
+  for (int q = 1;; ++q)
+    for (int p = 1; p <= q; ++p)
+      if (gcd_c(p, q) == 1 && idx-- == 0) return p;
+}
+__host__ __device__ constexpr int frac_den(int idx) {
+  for (int q = 1;; ++q)
+    for (int p = 1; p <= q; ++p)
+      if (gcd_c(p, q) == 1 && idx-- == 0) return q;
+}
+static_assert(frac_count(8) == 22 && frac_index(4, 8) == 1 && frac_num(5) == 3 && frac_den(5) == 4, "fractions");
+
+template <int NH>
+struct HighState {
+  float val[frac_count(NH)][4];
+  int row[frac_count(NH)];  // source row the values belong to (uniform)
+};
+
+// rho(P x, Q) for x >= 0
+template <int P, int Q>
+__device__ __forceinline__ int rho_pos(int x) {
+  return (int)((2u * P * (unsigned)x + Q) / (2u * Q));
+}
+
+// refresh fraction F and the ones after it for output row i
+template <int NH, int F>
+__device__ __forceinline__ void hi_refresh(HighState<NH>& st, const float* __restrict__ fop, int64_t ld, int z_max,
+                                           int i, const int (&colc)[4]) {
+  if constexpr (F < frac_count(NH)) {
+    constexpr int P = frac_num(F), Q = frac_den(F);
+    const int s = rho_pos<P, Q>(i < 0 ? -i : i);
+    const int srow = (i < 0 ? -s : s) + z_max;
+    if (srow != st.row[F]) {  // uniform
+      st.row[F] = srow;
+      const float* src = fop + (size_t)srow * ld;
+#pragma unroll
+      for (int a = 0; a < 4; ++a) st.val[F][a] = src[rho_pos<P, Q>(colc[a])];
+    }
+    hi_refresh<NH, F + 1>(st, fop, ld, z_max, i, colc);
+  }
+}
+
+// HP_K = terms m = 1..K in m order
+template <int NH, int K, int M>
+__device__ __forceinline__ void hi_sum(const HighState<NH>& st, float (&hp)[4]) {
+  if constexpr (M <= K) {
+    constexpr int FI = frac_index(M, K);
+#pragma unroll
+    for (int a = 0; a < 4; ++a) hp[a] = M == 1 ? st.val[FI][a] : hp[a] + st.val[FI][a];
+    hi_sum<NH, K, M + 1>(st, hp);
+  }
+}
+
+template <int NH, int K>
+__device__ __forceinline__ void hi_planes(const HighState<NH>& st, int r, int i, int rows, const int (&col)[4],
+                                          const bool (&in)[4], const float* __restrict__ ta,
+                                          fdas_cand* __restrict__ cands, int cap, int32_t* __restrict__ counts) {
+  if constexpr (K <= NH) {
+    float hp[4];
+    hi_sum<NH, K, 1>(st, hp);
+    const float t = ta[(K - 1) * rows + r];
+    unsigned bits = 0u;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) bits |= (in[a] && hp[a] > t) ? 1u << a : 0u;
+    wave_append(K, i, col, hp, bits, cands, cap, counts);
+    hi_planes<NH, K + 1>(st, r, i, rows, col, in, ta, cands, cap, counts);
+  }
+}
+
 template <int NH>
 __global__ __launch_bounds__(HS_THREADS) void k_harmsum_high(const float* __restrict__ fop, int64_t ld, int n,
-                                                             int z_max, const float* __restrict__ ta,
+                                                             int z_max, const int* __restrict__ tile_of_block,
+                                                             const float* __restrict__ ta,
                                                              fdas_cand* __restrict__ cands, int cap,
                                                              int32_t* __restrict__ counts) {
-  const int64_t g = (int64_t)blockIdx.x * HS_THREADS + threadIdx.x;
-  const int64_t j0 = g * 4;
-  if (j0 >= n) return;
+  const int tile = xt_tile(tile_of_block, n);
+  if (tile < 0) return;  // uniform
   const int rows = 2 * z_max + 1;
-  // columns past n - 1 (the ragged last group) read column n - 1 and are never emitted
-  int64_t jj[4];
+  int col[4], colc[4];
+  bool in[4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a) jj[a] = j0 + a < n ? j0 + a : n - 1;
+  for (int a = 0; a < 4; ++a) {
+    col[a] = tile * XT + (int)threadIdx.x + HS_THREADS * a;
+    in[a] = col[a] < n;
+    colc[a] = in[a] ? col[a] : n - 1;  // columns past n - 1 read column n - 1 and are never emitted
+  }
+  constexpr int NF = frac_count(NH);
+  HighState<NH> st;
+#pragma unroll
+  for (int f = 0; f < NF; ++f) st.row[f] = -1;
   for (int r = 0; r < rows; ++r) {
     const int i = r - z_max;
-#pragma unroll
-    for (int k = 1; k <= NH; ++k) {
-      float hp[4];
-#pragma unroll
-      for (int m = 1; m <= k; ++m) {
-        const float* src = fop + (size_t)(round_div((int64_t)m * i, k) + z_max) * ld;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          const float v = src[round_div((int64_t)m * jj[a], k)];
-          hp[a] = m == 1 ? v : hp[a] + v;
-        }
-      }
-      const float t = ta[(k - 1) * rows + r];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-        if (hp[a] > t && j0 + a < n) emit(k, i, (int)(j0 + a), hp[a], cands, cap, counts);
-    }
+    hi_refresh<NH, 0>(st, fop, ld, z_max, i, colc);
+    hi_planes<NH, 1>(st, r, i, rows, col, in, ta, cands, cap, counts);
   }
 }
 
@@ -695,7 +832,9 @@ hipError_t launch_harmsum_noalloc(const float* fop, int64_t n, int64_t ld, int z
   const int cols = 4 * HS_THREADS;
   const int T = (int)((n + cols - 1) / cols);
   const int per = (T + 7) / 8;
-  if (z_max == 42 && index == FDAS_HSUM_STRETCH) {
+  const bool ordered = (z_max == 42 && index == FDAS_HSUM_STRETCH) || index == FDAS_HSUM_FUNDAMENTAL ||
+                       index == FDAS_HSUM_HIGHEST;
+  if (ordered) {
     int top = 0;
     while ((1LL << (top + 1)) <= (int64_t)(T > 2 ? T - 1 : 1)) ++top;
     hipError_t e = launch_fill_i32(order, per * 8, -1, s);
@@ -793,18 +932,20 @@ hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, in
     if (e0 != hipSuccess) return e0;
   }
   if (index == FDAS_HSUM_FUNDAMENTAL || index == FDAS_HSUM_HIGHEST) {
-    const int64_t groups = (n + 3) / 4;
-    const unsigned blocks = (unsigned)((groups + HS_THREADS - 1) / HS_THREADS);
+    // column tiles of XT columns, in the order of wk.tile_of_block when given
+    const unsigned blocks =
+        wk.tile_of_block ? (unsigned)wk.blocks : (unsigned)((n + XT - 1) / XT);
+    const int* order = wk.tile_of_block;
     const bool fund = index == FDAS_HSUM_FUNDAMENTAL;
     switch (n_harm) {
-#define FDAS_HSX_CASE(NH)                                                                                      \
-  case NH:                                                                                                     \
-    if (fund)                                                                                                  \
-      hipLaunchKernelGGL(k_harmsum_fund<NH>, dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max, ta, \
-                         cands, cap, counts);                                                                  \
-    else                                                                                                       \
-      hipLaunchKernelGGL(k_harmsum_high<NH>, dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max, ta, \
-                         cands, cap, counts);                                                                  \
+#define FDAS_HSX_CASE(NH)                                                                                          \
+  case NH:                                                                                                         \
+    if (fund)                                                                                                      \
+      hipLaunchKernelGGL(k_harmsum_fund<NH>, dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max, order,  \
+                         ta, cands, cap, counts);                                                                  \
+    else                                                                                                           \
+      hipLaunchKernelGGL(k_harmsum_high<NH>, dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max, order,  \
+                         ta, cands, cap, counts);                                                                  \
     break;
       FDAS_HSX_CASE(1)
       FDAS_HSX_CASE(2)

@@ -130,3 +130,34 @@ def test_end_to_end_injection(index):
     for k in range(1, 5):
         cell = (k, z0, r0) if index == "fundamental" else (k, k * z0, k * r0)
         assert cell in gk, cell
+
+
+@pytest.mark.parametrize("index", sorted(MAPS))
+def test_dense_hits_and_capacity_overflow(index):
+    # most cells above threshold: every wave appends many records per plane
+    # at once; with a 16-record list the counts stay exact and the records
+    # kept are true candidates
+    n = 5000
+    rng = np.random.default_rng(3)
+    plane = (rng.exponential(size=(85, n)) * 5).astype(np.float32)
+    ta = oh.threshold_array(8, 42, 0.01).astype(np.float32)
+    ref = oh.candidates(plane, 8, ta=ta, index=index)
+    big = fdas.plan_create(n_max=1 << 16, hsum_index=MAPS[index], cand_capacity=1 << 20)
+    small = fdas.plan_create(n_max=1 << 16, hsum_index=MAPS[index], cand_capacity=16)
+    try:
+        got, counts = gpu_candidates(big, plane, ta=ta)
+        assert np.array_equal(counts, oh.plane_counts(ref))
+        _assert_same(got, ref)
+        cands, dcounts = fdas.alloc_cands(small, _dev())
+        fdas.harmonic_sum(small, _upload_plane(plane), n, cands, dcounts,
+                          ta=torch.from_numpy(ta).to(_dev()))
+        assert np.array_equal(dcounts.cpu().numpy(), oh.plane_counts(ref))
+        kept, _ = fdas.candidates(small, cands, dcounts, allow_overflow=True)
+        assert kept.size == 8 * 16
+        refset = set(zip(ref["harm"].tolist(), ref["z"].tolist(), ref["r"].tolist(),
+                         ref["power"].astype(np.float32).view(np.int32).tolist()))
+        assert all(k in refset for k in zip(kept["harm"].tolist(), kept["z"].tolist(), kept["r"].tolist(),
+                                            kept["power"].astype(np.float32).view(np.int32).tolist()))
+    finally:
+        big.destroy()
+        small.destroy()
