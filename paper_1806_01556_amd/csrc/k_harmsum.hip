@@ -149,12 +149,30 @@ __device__ __forceinline__ int xt_tile(const int* __restrict__ tile_of_block, in
   return (tile >= 0 && (int64_t)tile * XT < n) ? tile : -1;
 }
 
+// Raw buffer resource over part of one FOP row: loads at byte offsets >=
+// bytes read 0 (the hardware range check), so columns past n - 1 need no
+// compare.  The resource starts at the first column a workgroup reads, so
+// offsets stay below 32 KB whatever n is.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const float* base, int64_t cols_left) {
+  const uint32_t bytes = cols_left <= 0 ? 0u : (cols_left >= 16384 ? 65536u : (uint32_t)cols_left * 4u);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+__device__ __forceinline__ float row_load(__amdgpu_buffer_rsrc_t rs, int byte_off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rs, byte_off, 0, 0));
+}
+
 // Fundamental-anchored: HP_k(i, j) = HP_{k-1}(i, j) + FOP(k i, k j), a term
 // being 0 where (k i, k j) is outside the plane.  Cumulative in k.  A row's
-// loads (the fundamental and every harmonic's source row k i) are issued
-// together before its sums.
+// loads (the fundamental and every harmonic's source row k i inside the
+// plane) are issued together before its sums, as buffer loads whose range
+// check supplies the zeros of columns k j >= n.  Harmonic m of the tile
+// starting at column t0 reads columns m t0 + m (t + 256 a).  Six waves per
+// SIMD (80 VGPRs) hide the load latency best: 0.94 ms on a 2^22 plane against
+// 0.98 ms at five and 1.00 ms at eight (with spills); loading row r + 1
+// before the sums of row r (three waves) took 1.06 ms.
 template <int NH>
-__global__ __launch_bounds__(HS_THREADS) void k_harmsum_fund(const float* __restrict__ fop, int64_t ld, int n,
+__global__ __launch_bounds__(HS_THREADS, 6) void k_harmsum_fund(const float* __restrict__ fop, int64_t ld, int n,
                                                              int z_max, const int* __restrict__ tile_of_block,
                                                              const float* __restrict__ ta,
                                                              fdas_cand* __restrict__ cands, int cap,
@@ -162,41 +180,45 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_fund(const float* __rest
   const int tile = xt_tile(tile_of_block, n);
   if (tile < 0) return;  // uniform
   const int rows = 2 * z_max + 1;
+  const int64_t t0 = (int64_t)tile * XT;
+  const int t = (int)threadIdx.x;
   int col[4];
   bool in[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
-    col[a] = tile * XT + (int)threadIdx.x + HS_THREADS * a;
+    col[a] = (int)t0 + t + HS_THREADS * a;  // n <= 2^30, so no wrap
     in[a] = col[a] < n;
   }
   for (int r = 0; r < rows; ++r) {
     const int i = r - z_max;
     float v[NH + 1][4];
     {
-      const float* row = fop + (size_t)r * ld;
+      const __amdgpu_buffer_rsrc_t rs = row_rsrc(fop + (size_t)r * ld + t0, (int64_t)n - t0);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) v[1][a] = in[a] ? row[col[a]] : 0.0f;
+      for (int a = 0; a < 4; ++a) v[1][a] = row_load(rs, 4 * (t + HS_THREADS * a));
     }
 #pragma unroll
     for (int m = 2; m <= NH; ++m) {
       const int si = m * i;
-      const bool rin = si >= -z_max && si <= z_max;  // uniform
-      const float* src = fop + (size_t)(rin ? si + z_max : 0) * ld;
+      if (si >= -z_max && si <= z_max) {  // uniform
+        const __amdgpu_buffer_rsrc_t rs =
+            row_rsrc(fop + (size_t)(si + z_max) * ld + m * t0, (int64_t)n - m * t0);
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int sj = m * col[a];  // < 2^31: the plan keeps NH * n_max below it
-        v[m][a] = (rin && sj < n) ? src[sj] : 0.0f;
+        for (int a = 0; a < 4; ++a) v[m][a] = row_load(rs, 4 * m * (t + HS_THREADS * a));
+      } else {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) v[m][a] = 0.0f;
       }
     }
     float hp[4];
 #pragma unroll
     for (int m = 1; m <= NH; ++m) {
-      const float t = ta[(m - 1) * rows + r];
+      const float th = ta[(m - 1) * rows + r];
       unsigned bits = 0u;
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
         hp[a] = m == 1 ? v[1][a] : hp[a] + v[m][a];
-        bits |= (in[a] && hp[a] > t) ? 1u << a : 0u;
+        bits |= (in[a] && hp[a] > th) ? 1u << a : 0u;
       }
       wave_append(m, i, col, hp, bits, cands, cap, counts);
     }
@@ -245,27 +267,34 @@ struct HighState {
   int row[frac_count(NH)];  // source row the values belong to (uniform)
 };
 
-// rho(P x, Q) for x >= 0
-template <int P, int Q>
+// rho(P x, Q) for x >= 0.  Narrow: 2 P x + Q < 2^32 (n * 2 NH < 2^32).  Wide,
+// any x < 2^31: with x = Q u + w (w < Q), P x / Q = P u + P w / Q, so the
+// rounding only involves P w < P Q.
+template <int P, int Q, bool WIDE>
 __device__ __forceinline__ int rho_pos(int x) {
-  return (int)((2u * P * (unsigned)x + Q) / (2u * Q));
+  if constexpr (WIDE) {
+    const unsigned u = (unsigned)x / Q, w = (unsigned)x - u * Q;
+    return (int)(P * u + (2u * P * w + Q) / (2u * Q));
+  } else {
+    return (int)((2u * P * (unsigned)x + Q) / (2u * Q));
+  }
 }
 
 // refresh fraction F and the ones after it for output row i
-template <int NH, int F>
+template <int NH, bool WIDE, int F>
 __device__ __forceinline__ void hi_refresh(HighState<NH>& st, const float* __restrict__ fop, int64_t ld, int z_max,
                                            int i, const int (&colc)[4]) {
   if constexpr (F < frac_count(NH)) {
     constexpr int P = frac_num(F), Q = frac_den(F);
-    const int s = rho_pos<P, Q>(i < 0 ? -i : i);
+    const int s = rho_pos<P, Q, false>(i < 0 ? -i : i);
     const int srow = (i < 0 ? -s : s) + z_max;
     if (srow != st.row[F]) {  // uniform
       st.row[F] = srow;
       const float* src = fop + (size_t)srow * ld;
 #pragma unroll
-      for (int a = 0; a < 4; ++a) st.val[F][a] = src[rho_pos<P, Q>(colc[a])];
+      for (int a = 0; a < 4; ++a) st.val[F][a] = src[rho_pos<P, Q, WIDE>(colc[a])];
     }
-    hi_refresh<NH, F + 1>(st, fop, ld, z_max, i, colc);
+    hi_refresh<NH, WIDE, F + 1>(st, fop, ld, z_max, i, colc);
   }
 }
 
@@ -296,7 +325,7 @@ __device__ __forceinline__ void hi_planes(const HighState<NH>& st, int r, int i,
   }
 }
 
-template <int NH>
+template <int NH, bool WIDE>
 __global__ __launch_bounds__(HS_THREADS) void k_harmsum_high(const float* __restrict__ fop, int64_t ld, int n,
                                                              int z_max, const int* __restrict__ tile_of_block,
                                                              const float* __restrict__ ta,
@@ -319,7 +348,7 @@ __global__ __launch_bounds__(HS_THREADS) void k_harmsum_high(const float* __rest
   for (int f = 0; f < NF; ++f) st.row[f] = -1;
   for (int r = 0; r < rows; ++r) {
     const int i = r - z_max;
-    hi_refresh<NH, 0>(st, fop, ld, z_max, i, colc);
+    hi_refresh<NH, WIDE, 0>(st, fop, ld, z_max, i, colc);
     hi_planes<NH, 1>(st, r, i, rows, col, in, ta, cands, cap, counts);
   }
 }
@@ -937,15 +966,19 @@ hipError_t launch_harmsum(const float* fop, int64_t n, int64_t ld, int z_max, in
         wk.tile_of_block ? (unsigned)wk.blocks : (unsigned)((n + XT - 1) / XT);
     const int* order = wk.tile_of_block;
     const bool fund = index == FDAS_HSUM_FUNDAMENTAL;
+    const bool narrow = 2 * (int64_t)n_harm * n < ((int64_t)1 << 32);  // rho(m j, k) in 32-bit arithmetic
     switch (n_harm) {
 #define FDAS_HSX_CASE(NH)                                                                                          \
   case NH:                                                                                                         \
     if (fund)                                                                                                      \
       hipLaunchKernelGGL(k_harmsum_fund<NH>, dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max, order,  \
                          ta, cands, cap, counts);                                                                  \
+    else if (narrow)                                                                                               \
+      hipLaunchKernelGGL((k_harmsum_high<NH, false>), dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max, \
+                         order, ta, cands, cap, counts);                                                           \
     else                                                                                                           \
-      hipLaunchKernelGGL(k_harmsum_high<NH>, dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max, order,  \
-                         ta, cands, cap, counts);                                                                  \
+      hipLaunchKernelGGL((k_harmsum_high<NH, true>), dim3(blocks), dim3(HS_THREADS), 0, s, fop, ld, (int)n, z_max,  \
+                         order, ta, cands, cap, counts);                                                           \
     break;
       FDAS_HSX_CASE(1)
       FDAS_HSX_CASE(2)

@@ -161,3 +161,28 @@ def test_dense_hits_and_capacity_overflow(index):
     finally:
         big.destroy()
         small.destroy()
+
+
+@pytest.mark.timeout(400)
+@pytest.mark.parametrize("index", sorted(MAPS))
+def test_wide_single_row_plane(index):
+    # one template row (z_max = 0) admits spectra past 2^28 bins: the
+    # highest-anchored map then rounds m j / k in its wide form and the
+    # fundamental-anchored map's stride-k reads run past 2^31 bytes; three
+    # column windows (start, the 2^28 boundary, end) against the oracle
+    n = (1 << 28) + 5000
+    plan = fdas.plan_create(z_max=0, n_max=n, hsum_index=MAPS[index], cand_capacity=1 << 20)
+    try:
+        rng = np.random.default_rng(28)
+        plane = rng.standard_exponential(size=(1, n), dtype=np.float32)
+        ta = oh.threshold_array(8, 0, 2e-3).astype(np.float32)  # ~0.5 M cells per plane
+        got, _ = gpu_candidates(plan, plane, ta=ta)
+        print(f"wide plane {index}: {got.size} candidates", flush=True)
+        for lo, hi in [(0, 4000), ((1 << 28) - 3000, (1 << 28) + 1000), (n - 4000, n)]:
+            cols = np.arange(lo, hi)
+            ref = oh.candidates(plane, 8, ta=ta, cols=cols, index=index)
+            sel = got[(got["r"] >= lo) & (got["r"] < hi)]
+            assert ref.size > 5
+            _assert_same(sel, ref)
+    finally:
+        plan.destroy()
