@@ -25,6 +25,7 @@ full 2^22 workload by N log2 N.
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -107,8 +108,6 @@ def cpu_baseline(spec, n_full, runs=3):
     length by N log2 N (the oracle's time is its 86 FFTs of about N points;
     the linear harmonic sum makes this scaling slightly pessimistic for the
     CPU)."""
-    import math
-
     from oracle import fop as ofop
     from oracle import harmonic as oh
 
@@ -304,36 +303,65 @@ def _keys(c):
     return np.sort(k)
 
 
-def bench_prescreen(args, torch, fdas, synth, dev):
-    """Learned block pre-screen at the pre-screen workload's sizes: train on
-    10,000 oracle-labelled spectra (tests/golden/prescreen_labels.txt, 2^16
-    bins each, regenerated from their seeds; the 240 further labelled spectra
-    pick the logit threshold), then search 256 spectra of 2^22 bins on the
-    flagged blocks and their harmonic multiples, against the plain search of
-    the same spectra.  Recall is reported three ways: over every candidate
-    cell of the plain search at the configured p_fa (1e-6), over its
-    significant cells (power above T_k at a per-cell false-alarm probability
-    of 1e-12, cells a screen can be asked to keep), and per injected pulsar
-    the plain search detects."""
-    path = os.path.join(ROOT, "tests", "golden", "prescreen_labels.txt")
+def _load_labels(name):
+    """(recipe, [(i, block label string)]) of a pre-screen label fixture; rows
+    stored as hex digits (block 0 in the leading bit) are expanded."""
+    path = os.path.join(ROOT, "tests", "golden", name)
     with open(path) as f:
         lines = f.read().splitlines()
     recipe = json.loads(next(l for l in lines if l.startswith("# recipe: "))[len("# recipe: "):])
-    rows = [l.split() for l in lines if l and not l.startswith("#")]
+    nb = recipe["n"] // recipe["block"]
+    rows = []
+    for l in lines:
+        if not l or l.startswith("#"):
+            continue
+        i, b = l.split()
+        if len(b) != nb:
+            b = format(int(b, 16), "0%db" % nb)
+        rows.append((int(i), b))
+    return recipe, rows
+
+
+def bench_prescreen(args, torch, fdas, synth, dev):
+    """Learned block pre-screen at the pre-screen workload's sizes: train on
+    10,000 oracle-labelled spectra of 2^20 bins (tests/golden/
+    prescreen_labels_2p20.txt, regenerated from their seeds; the 240 further
+    labelled spectra pick the logit threshold), then search 256 spectra of
+    2^22 bins on the flagged blocks and their harmonic multiples, against the
+    plain search of the same spectra.  Recall is reported three ways: over
+    every candidate cell of the plain search at the configured p_fa (1e-6),
+    over its significant cells (power above T_k at a per-cell false-alarm
+    probability of 1e-12, cells a screen can be asked to keep), and per
+    injected pulsar the plain search detects."""
+    name = "prescreen_labels_2p20.txt" if args.train_set == "2p20" else "prescreen_labels.txt"
+    recipe, rows = _load_labels(name)
     nspec = len(rows)
     n_tr = recipe["n"]
     bpb = n_tr // 4096
     workers = cpu_workers()
-    t_syn = time.perf_counter()
-    specs = _spawn_map(_train_spectrum, [(int(i), recipe) for i, _ in rows], workers)
-    t_syn = time.perf_counter() - t_syn
     ps = fdas.Prescreen(max_batch=1024)  # one inference call covers a 2^22-bin spectrum
+    # features of every block of every labelled spectrum stay on the device
+    # (10,240 x 256 blocks x 16 KB = 43 GB at 2^20 bins); spectra are made by
+    # worker processes in chunks and dropped once their features are formed
     feats = torch.empty((nspec * bpb, 4096), dtype=torch.float32, device=dev)
     labels = torch.tensor([float(c) for _, bits in rows for c in bits], dtype=torch.float32, device=dev)
-    for k, sp in enumerate(specs):
-        ps.features(torch.from_numpy(sp).to(dev), n_tr, bpb, feats[k * bpb:(k + 1) * bpb])
-    del specs
+    t_syn = time.perf_counter()
+    chunk = 256
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        for c0 in range(0, nspec, chunk):
+            part = rows[c0:c0 + chunk]
+            specs = list(ex.map(_train_spectrum, [(i, recipe) for i, _ in part],
+                                chunksize=max(1, len(part) // (2 * workers))))
+            for k, sp in enumerate(specs):
+                kk = c0 + k
+                ps.features(torch.from_numpy(sp).to(dev), n_tr, bpb, feats[kk * bpb:(kk + 1) * bpb])
+            del specs
+            if (c0 // chunk) % 8 == 7:
+                print(f"prescreen: {c0 + len(part)}/{nspec} training spectra made", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
+    t_syn = time.perf_counter() - t_syn
     n_train = min(args.train_spectra, nspec - 1)
     tr = np.arange(n_train * bpb)
     va = np.arange(n_train * bpb, nspec * bpb)
@@ -511,9 +539,7 @@ def bench_prescreen(args, torch, fdas, synth, dev):
                    "val_spectra": nspec - n_train, "train_n": n_tr, "epochs": args.epochs, "train_steps": steps,
                    "pos_weight": round(pos_weight, 3), "p_fa": 1e-6, "p_label": recipe.get("p_label"),
                    "p_sig": recipe["p_sig"], "test_seeds": f"{PRESCREEN_TEST_SEED0}+i",
-                   "note": "training spectra have 2^16 bins instead of 2^20 (the FP64 oracle labels 10,240 of "
-                           "them in minutes; 2^20 would take about 14 CPU hours); the block statistics "
-                           "are the same"},
+                   "train_label_file": name, "train_seeds": f"{recipe['seed0']}+i"},
         "plain_spectra_per_s": round(T / t_plain, 3),
         "speedup_vs_plain": round(t_plain / t_pre, 3),
         "recall_all_cells": head["recall_all_cells"],
@@ -548,6 +574,8 @@ def main():
                          "wait) or fdas_candidates (DMA copy, two waits); auto = copy with steps in flight "
                          "(no compute units held by PCIe writes beside the next step's kernels), mapped "
                          "otherwise")
+    ap.add_argument("--ols-chunk", type=int, default=0, choices=(0, 2048, 4096, 8192),
+                    help="overlap-save chunk length C of the plans (0 = the library default, 4096)")
     ap.add_argument("--pipeline", type=int, default=2,
                     help="steps in flight in the timed region: with 2 (default), step k+1's kernels are "
                          "queued on a second plan and stream before step k's candidates are read back; "
@@ -561,6 +589,9 @@ def main():
                          "pre-screen on oracle-labelled spectra, then search 2^22-bin spectra on flagged blocks; "
                          "index-maps: the harmonic sum of one 2^22-bin plane under each index map")
     ap.add_argument("--epochs", type=int, default=8, help="prescreen workload: training epochs")
+    ap.add_argument("--train-set", choices=("2p20", "2p16"), default="2p20",
+                    help="prescreen workload: labelled spectra of 2^20 bins (tests/golden/prescreen_labels_2p20.txt, "
+                         "default) or of 2^16 bins (tests/golden/prescreen_labels.txt)")
     ap.add_argument("--train-spectra", type=int, default=10000,
                     help="prescreen workload: labelled spectra to train on (the rest pick the threshold)")
     ap.add_argument("--test-spectra", type=int, default=256, help="prescreen workload: 2^22-bin test spectra")
@@ -600,7 +631,8 @@ def main():
     # in flight step k uses set k % P, so step k's kernels run while step
     # k-1's candidates are ordered and copied back (a plan is used by one
     # stream at a time)
-    plans = [fdas.plan_create(n_max=n, method=method, precision=precision) for _ in range(NP)]
+    C = args.ols_chunk or 4096
+    plans = [fdas.plan_create(n_max=n, method=method, precision=precision, ols_chunk=C) for _ in range(NP)]
     fops = [fdas.alloc_fop(plans[i], n, dev) for i in range(NP)]
     bufs = [fdas.alloc_cands(plans[i], dev) for i in range(NP)]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(NP - 1)]
@@ -680,11 +712,11 @@ def main():
                 "note": "two plans on two streams: one spectrum's readback and harmonic sum overlap the "
                         "next one's convolution"}
 
-    V = 4096 - 393                                    # valid outputs per 4096-point chunk
+    V = C - 393                                      # valid outputs per C-point chunk
     hs_bytes = 4 * 85 * n                            # FOP read once
     conv_bytes = 8 * n + 4 * 85 * n                  # spectrum read + FOP write
     if args.method == "ols":
-        conv_flop = 85 * 5 * 4096 * 12 / V * n      # algorithmic FFT flops of one launch
+        conv_flop = 85 * 5 * C * math.log2(C) / V * n  # algorithmic FFT flops of one launch
         conv = {"name": "k_ols_conv", "bound": "alu", "peak": FP32_VECTOR_PEAK_TF, "file": "k_ols_conv.hip"}
     elif args.method == "direct":
         taps = sum(2 * (8 + (9 * abs(z) + 1) // 2) for z in range(-42, 43))
@@ -718,7 +750,8 @@ def main():
         "peak": dom["peak"],
         "unit": dom["unit"],
         "frac": round(dom["achieved"] / dom["peak"], 4),
-        "traffic": read_traffic(dom["file"], "bytes_per_launch"),
+        # the counters were taken at the default chunk length
+        "traffic": read_traffic(dom["file"], "bytes_per_launch") if C == 4096 or dom_name != "k_ols_conv" else None,
     }
     # the same kernel timed in the serial pass (no other step's kernels beside it)
     conv_work = conv_flop / 1e12
@@ -754,7 +787,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "ska_single_spectrum_2^22", "n": n, "templates": 85, "z_max": 42,
                    "harmonics": 8, "p_fa": 1e-6, "pulsars": len(pulsars), "seed": 2,
-                   "method": {"ols": "ols_fft_c4096", "direct": "direct_mfma_fp32",
+                   "method": {"ols": f"ols_fft_c{C}", "direct": "direct_mfma_fp32",
                               "direct-fp16": "direct_mfma_split_fp16",
                               "direct-bf16": "direct_mfma_split_bf16"}[args.method],
                    "pipeline": P, "readback": args.readback},

@@ -3,8 +3,9 @@ no allocation) against fdas_harmonic_sum on the same FOP: identical counts,
 candidate indices and power bits, on two calls in a row, the second with a
 smaller input (the static array keeps the first call's contents), for the
 85-row stretched sum, for a plan with another row count (the generic kernel,
-which uses no scratch) and a row-dependent threshold array; n above the
-static capacity is rejected before anything runs.
+which uses no scratch) and a row-dependent threshold array, for the two other
+index maps (their tile order lives in the static array); n above the static
+capacity is rejected before anything runs.
 """
 
 import numpy as np
@@ -75,6 +76,20 @@ def test_noalloc_generic_rows_and_row_dependent_thresholds():
         _compare(plan, spec, ta=ta)
         spec2, _ = synth.make_spectrum(5001, 73, n_random=1, r_range=(500, 2000), snr_range=(8, 20))
         _compare(plan, spec2)
+    finally:
+        plan.destroy()
+
+
+@pytest.mark.parametrize("index", [fdas.HSUM_FUNDAMENTAL, fdas.HSUM_HIGHEST])
+def test_noalloc_other_index_maps(index):
+    # the index-map kernels take their tile order from the static array too
+    plan = fdas.plan_create(n_max=1 << 22, hsum_index=index)
+    try:
+        big, _ = synth.ska(n=1 << 22, seed=2)
+        nb = _compare(plan, big)
+        small, _ = synth.make_spectrum(300_001, 74, n_random=3, r_range=(2000, 1.2e5), snr_range=(8, 20))
+        ns = _compare(plan, small)
+        assert nb > 0 and ns > 0
     finally:
         plan.destroy()
 
