@@ -589,6 +589,11 @@ def main():
                          "otherwise")
     ap.add_argument("--ols-chunk", type=int, default=0, choices=(0, 2048, 4096, 8192),
                     help="overlap-save chunk length C of the plans (0 = the library default, 4096)")
+    ap.add_argument("--step-order", choices=("overlap", "chain", "staged"), default="overlap",
+                    help="with steps in flight: overlap = the kernels of the two streams share the chip; chain = a "
+                         "step's convolution waits on the device for the previous step's harmonic sum; staged = "
+                         "chain, and the previous step's ordering and readback also wait for this step's "
+                         "convolution (they run beside its harmonic sum)")
     ap.add_argument("--pipeline", type=int, default=2,
                     help="steps in flight in the timed region: with 2 (default), step k+1's kernels are "
                          "queued on a second plan and stream before step k's candidates are read back; "
@@ -650,15 +655,28 @@ def main():
     bufs = [fdas.alloc_cands(plans[i], dev) for i in range(NP)]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(NP - 1)]
 
+    # --step-order: "overlap" leaves the two streams' kernels to share the
+    # chip; "chain" makes step k's convolution wait (on the device) for step
+    # k-1's harmonic sum, so only the ordering and readback of a step overlap
+    # the next step's kernels; "staged" also makes the ordering of step k-1
+    # wait for step k's convolution, so the convolution runs alone and the
+    # ordering runs beside the harmonic sum
+    hs_done = [torch.cuda.Event() for _ in range(NP)]
+    conv_done = [torch.cuda.Event() for _ in range(NP)]
+
     def enqueue(k, ev=None, P=P):
         i = k % P
         st = streams[i]
+        if args.step_order in ("chain", "staged") and P > 1 and k > 0:
+            st.wait_event(hs_done[(k - 1) % P])
         if ev:
             ev[0].record(st)
         fdas.convolve(plans[i], x, fops[i], n=n, stream=st)
+        conv_done[i].record(st)
         if ev:
             ev[1].record(st)
         fdas.harmonic_sum(plans[i], fops[i], n, bufs[i][0], bufs[i][1], stream=st)
+        hs_done[i].record(st)
         if ev:
             ev[2].record(st)
 
@@ -679,6 +697,8 @@ def main():
         for k in range(steps):
             enqueue(k, evs[k] if evs else None, P)
             if k >= P - 1:
+                if args.step_order == "staged" and P > 1:
+                    streams[(k - P + 1) % P].wait_event(conv_done[k % P])
                 out = readback(k - P + 1, P)
         for k in range(max(0, steps - P + 1), steps):
             out = readback(k, P)
@@ -803,7 +823,7 @@ def main():
                    "method": {"ols": f"ols_fft_c{C}", "direct": "direct_mfma_fp32",
                               "direct-fp16": "direct_mfma_split_fp16",
                               "direct-bf16": "direct_mfma_split_bf16"}[args.method],
-                   "pipeline": P, "readback": args.readback},
+                   "pipeline": P, "readback": args.readback, "step_order": args.step_order},
         "roofline": roof,
         "roofline_isolated": roof_iso,
         "stages_ms": {"convolve": round(conv_ms, 4), "harmonic_sum": round(hs_ms, 4),
