@@ -8,8 +8,10 @@
 //
 // Sums are FP32 in k order (no reassociation, no contraction: there are only
 // additions), so every kernel here is bit-identical to a sequential FP32 sum.
-// Each thread owns 4 adjacent columns j0..j0+3; for k >= 2 those columns read
-// at most two adjacent source columns (floor(j/k) spans <= 2 values).
+// In the stretch-map kernels each thread owns 4 adjacent columns j0..j0+3;
+// for k >= 2 those columns read at most two adjacent source columns
+// (floor(j/k) spans <= 2 values).  The kernels of the other index maps
+// interleave a thread's columns across the wave instead (see there).
 
 #include "fdas_internal.h"
 
