@@ -589,6 +589,8 @@ def main():
                          "otherwise")
     ap.add_argument("--ols-chunk", type=int, default=0, choices=(0, 2048, 4096, 8192),
                     help="overlap-save chunk length C of the plans (0 = the library default, 4096)")
+    ap.add_argument("--emit-workgroups", type=int, default=0,
+                    help="workgroups of the harmonic sum's candidate emission (64..16384; 0 = the library default)")
     ap.add_argument("--step-order", choices=("overlap", "chain", "staged"), default="overlap",
                     help="with steps in flight: overlap = the kernels of the two streams share the chip; chain = a "
                          "step's convolution waits on the device for the previous step's harmonic sum; staged = "
@@ -651,6 +653,9 @@ def main():
     # stream at a time)
     C = args.ols_chunk or 4096
     plans = [fdas.plan_create(n_max=n, method=method, precision=precision, ols_chunk=C) for _ in range(NP)]
+    if args.emit_workgroups:
+        for p_ in plans:
+            fdas.set_tuning(p_, emit_workgroups=args.emit_workgroups)
     fops = [fdas.alloc_fop(plans[i], n, dev) for i in range(NP)]
     bufs = [fdas.alloc_cands(plans[i], dev) for i in range(NP)]
     streams = [torch.cuda.current_stream()] + [torch.cuda.Stream() for _ in range(NP - 1)]
@@ -823,7 +828,8 @@ def main():
                    "method": {"ols": f"ols_fft_c{C}", "direct": "direct_mfma_fp32",
                               "direct-fp16": "direct_mfma_split_fp16",
                               "direct-bf16": "direct_mfma_split_bf16"}[args.method],
-                   "pipeline": P, "readback": args.readback, "step_order": args.step_order},
+                   "pipeline": P, "readback": args.readback, "step_order": args.step_order,
+                   "emit_workgroups": args.emit_workgroups or 1024},
         "roofline": roof,
         "roofline_isolated": roof_iso,
         "stages_ms": {"convolve": round(conv_ms, 4), "harmonic_sum": round(hs_ms, 4),
