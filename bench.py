@@ -591,11 +591,12 @@ def main():
                     help="overlap-save chunk length C of the plans (0 = the library default, 4096)")
     ap.add_argument("--emit-workgroups", type=int, default=0,
                     help="workgroups of the harmonic sum's candidate emission (64..16384; 0 = the library default)")
-    ap.add_argument("--step-order", choices=("overlap", "chain", "staged"), default="overlap",
+    ap.add_argument("--step-order", choices=("overlap", "chain", "staged", "hs-chain"), default="overlap",
                     help="with steps in flight: overlap = the kernels of the two streams share the chip; chain = a "
                          "step's convolution waits on the device for the previous step's harmonic sum; staged = "
                          "chain, and the previous step's ordering and readback also wait for this step's "
-                         "convolution (they run beside its harmonic sum)")
+                         "convolution (they run beside its harmonic sum); hs-chain = only a step's harmonic sum "
+                         "waits for the previous one")
     ap.add_argument("--pipeline", type=int, default=2,
                     help="steps in flight in the timed region: with 2 (default), step k+1's kernels are "
                          "queued on a second plan and stream before step k's candidates are read back; "
@@ -665,7 +666,8 @@ def main():
     # k-1's harmonic sum, so only the ordering and readback of a step overlap
     # the next step's kernels; "staged" also makes the ordering of step k-1
     # wait for step k's convolution, so the convolution runs alone and the
-    # ordering runs beside the harmonic sum
+    # ordering runs beside the harmonic sum; "hs-chain" only keeps two
+    # harmonic sums from running at once
     hs_done = [torch.cuda.Event() for _ in range(NP)]
     conv_done = [torch.cuda.Event() for _ in range(NP)]
 
@@ -680,6 +682,8 @@ def main():
         conv_done[i].record(st)
         if ev:
             ev[1].record(st)
+        if args.step_order == "hs-chain" and P > 1 and k > 0:
+            st.wait_event(hs_done[(k - 1) % P])
         fdas.harmonic_sum(plans[i], fops[i], n, bufs[i][0], bufs[i][1], stream=st)
         hs_done[i].record(st)
         if ev:
