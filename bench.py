@@ -741,6 +741,16 @@ def main():
     conv_ms_serial = float(np.mean([e[0].elapsed_time(e[1]) for e in sevs]))
     hs_ms_serial = float(np.mean([e[1].elapsed_time(e[2]) for e in sevs]))
 
+    # the candidate readback alone (ordering on the device + copy of the
+    # records to the host), after the harmonic sum has finished
+    rb_ms = []
+    for k in range(5):
+        enqueue(0)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        readback(0)
+        rb_ms.append(1e3 * (time.perf_counter() - t3))
+
     # two steps in flight (two plans and streams), untimed per kernel
     pipe = None
     if P == 1:
@@ -842,6 +852,9 @@ def main():
         "stages_median_ms": {"convolve": round(float(np.median([e[0].elapsed_time(e[1]) for e in evs])), 4),
                              "harmonic_sum": round(float(np.median([e[1].elapsed_time(e[2]) for e in evs])), 4)},
         "serial_ms_per_step": round(serial_ms, 4),
+        "readback_ms": {"median": round(float(np.median(rb_ms)), 4), "readback": args.readback,
+                        "note": "candidate ordering on the device and copy to the host, timed alone after the "
+                                "harmonic sum (inside every step above)"},
         "pipelined_2": pipe,
         "serial_stages_ms": {"convolve": round(conv_ms_serial, 4), "harmonic_sum": round(hs_ms_serial, 4)},
         "kernels": {k: {"avg_ms": round(v["ms"], 4), "achieved": round(v["achieved"], 3), "unit": v["unit"],
