@@ -484,13 +484,15 @@ def bench_prescreen(args, torch, fdas, synth, dev):
     def recall(st, key):
         return st[key + "_hit"] / max(st[key], 1)
 
-    # the recall rule on the held-out spectra (2^20 bins, seeds of the label recipe)
-    held = _spawn_map(_val_spectrum, [(i, recipe) for i, _ in rows[n_train:]], workers)
+    # the recall rule on held-out spectra of the label recipe: the first 240
+    # after the training set (all of them at the default sizes)
+    n_held = min(240, nspec - n_train)
+    held = _spawn_map(_val_spectrum, [(i, recipe) for i, _ in rows[n_train:n_train + n_held]], workers)
     xs_val = [torch.from_numpy(sp).to(dev) for sp, _ in held]
     puls_val = [pl for _, pl in held]
     del held
     grid = [(f"g{k}", float(np.quantile(lv[pos_v], q))) for k, q in enumerate(np.linspace(0.005, 0.5, 40))]
-    st_val, _ = evaluate(xs_val, puls_val, n_tr, grid)
+    st_val, _ = evaluate(xs_val, puls_val, n_tr, grid, progress="held-out")
     from scipy.stats import beta
 
     def lower95(k, m):
@@ -594,7 +596,7 @@ def bench_prescreen(args, torch, fdas, synth, dev):
         "dtype": "f32 search, bf16 network weights",
         "data": "synthetic",
         "config": {"workload": "prescreen_2^22", "test_spectra": T, "train_spectra": n_train,
-                   "val_spectra": nspec - n_train, "train_n": n_tr, "epochs": args.epochs, "train_steps": steps,
+                   "val_spectra": nspec - n_train, "val_search_spectra": n_held, "train_n": n_tr, "epochs": args.epochs, "train_steps": steps,
                    "pos_weight": round(pos_weight, 3), "p_fa": 1e-6, "p_label": recipe.get("p_label"),
                    "p_sig": recipe["p_sig"], "test_seeds": f"{PRESCREEN_TEST_SEED0}+i",
                    "train_label_file": label_file, "train_seeds": f"{recipe['seed0']}+i"},
